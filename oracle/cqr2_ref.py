@@ -1,0 +1,166 @@
+"""Plain CPU FP64 CholeskyQR2 — the oracle the HIP path is checked against.
+
+Test infrastructure: imported only by tests, the smoke check and the
+benchmark's CPU-baseline leg.  Written from the paper (Hutter & Solomonik,
+"Communication-avoiding CholeskyQR2 for rectangular matrices"):
+
+* sequential routines and their costs: Section "Preliminaries"
+  (Syrk = AᵀA costs m n^2, MM = AB costs 2 m n k);
+* recursive Cholesky, recursive triangular inverse and their combination
+  CholInv: Section "Cholesky Factorization", Algorithm 2;
+* CholeskyQR (CQR): Algorithm 4; CholeskyQR2 (CQR2): Algorithm 5.
+
+Everything is IEEE FP64 with numpy's library GEMM as the only primitive; no
+blocking, fusion or reordering beyond the recursive halving that Algorithm 2
+itself prescribes.  Readings where the paper is silent:
+
+* Syrk produces the lower triangle; the upper is never read (Alg. 2 reads A11,
+  A21, A22 only).  Here the full symmetric W is returned for convenience.
+* Odd n is split at h = floor(n/2) (the paper writes n/2).
+* The recursion goes down to n = 1 exactly as Algorithm 2's base case.
+* A non-positive or NaN pivot (the paper assumes SPD input) raises
+  ``NotSPD(j)`` with the 1-based column j, following LAPACK potrf's info.
+* Q is formed by multiplying by the explicit inverse R^{-1} (Algorithm 4's MM),
+  not by a triangular solve.
+* The second pass factors the stored Q1 (in the mixed form: the FP32 values,
+  converted exactly to FP64).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+class NotSPD(ArithmeticError):
+    """Cholesky breakdown: pivot at 1-based column ``j`` is <= 0 or NaN."""
+
+    def __init__(self, j: int):
+        super().__init__(f"matrix is not numerically SPD (pivot {j})")
+        self.j = j
+
+
+def syrk(a: np.ndarray) -> np.ndarray:
+    """W = AᵀA (Preliminaries, Syrk).  Returns the symmetric n x n W in FP64.
+
+    The lower triangle is the product itself; the upper triangle is mirrored
+    from it so no consumer can depend on it.
+    """
+    a = np.asarray(a, dtype=np.float64)
+    w = a.T @ a
+    low = np.tril(w)
+    return low + np.tril(w, -1).T
+
+
+def cholinv(a: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
+    """[L, Y] = CholInv(A) (Algorithm 2): A = L Lᵀ with L lower, Y = L^{-1}.
+
+    Steps, for A split into h x h and (n-h) x (n-h) diagonal blocks:
+      base case n == 1: L = sqrt(a), Y = 1 / L;
+      L11, Y11 = CholInv(A11);
+      L21 = A21 Y11ᵀ;
+      L22, Y22 = CholInv(A22 - L21 L21ᵀ);
+      Y21 = -Y22 (L21 Y11)   (the product order of Algorithm 3's last two MMs).
+    Only the lower triangle of ``a`` is read.
+    """
+    a = np.asarray(a, dtype=np.float64)
+    n = a.shape[0]
+    if a.shape != (n, n):
+        raise ValueError("CholInv needs a square matrix")
+    if n == 0:
+        return np.zeros((0, 0)), np.zeros((0, 0))
+    if n == 1:
+        piv = a[0, 0]
+        if not piv > 0.0:          # catches <= 0 and NaN
+            raise NotSPD(1)
+        l = math.sqrt(piv)
+        return np.array([[l]]), np.array([[1.0 / l]])
+    h = n // 2
+    l11, y11 = cholinv(a[:h, :h])
+    l21 = a[h:, :h] @ y11.T
+    schur = a[h:, h:] - l21 @ l21.T
+    try:
+        l22, y22 = cholinv(schur)
+    except NotSPD as e:
+        raise NotSPD(e.j + h) from None
+    u = l21 @ y11
+    y21 = -(y22 @ u)
+    l = np.zeros((n, n))
+    y = np.zeros((n, n))
+    l[:h, :h] = l11
+    l[h:, :h] = l21
+    l[h:, h:] = l22
+    y[:h, :h] = y11
+    y[h:, :h] = y21
+    y[h:, h:] = y22
+    return l, y
+
+
+def cqr(a: np.ndarray):
+    """[Q, R] = CQR(A) (Algorithm 4).
+
+    W = Syrk(A); Rᵀ, R^{-T} = CholInv(W); Q = MM(A, R^{-1}).
+    Returns (Q, R, R^{-1}).
+    """
+    a = np.asarray(a, dtype=np.float64)
+    w = syrk(a)
+    l, y = cholinv(w)
+    r = l.T.copy()
+    rinv = y.T.copy()
+    q = a @ rinv
+    return q, r, rinv
+
+
+def upper_product(r2: np.ndarray, r1: np.ndarray) -> np.ndarray:
+    """R = MM(R2, R1) for two upper-triangular factors (Algorithm 5, last line)."""
+    return np.asarray(r2, dtype=np.float64) @ np.asarray(r1, dtype=np.float64)
+
+
+def cqr2(a: np.ndarray, return_intermediates: bool = False):
+    """[Q, R] = CQR2(A) (Algorithm 5): two CQR passes, then R = R2 R1.
+
+    With ``return_intermediates`` also returns a dict with W1, R1, R1^{-1},
+    Q1, W2, R2, R2^{-1}.  A breakdown in the second pass is reported as
+    ``NotSPD(n + j)``.
+    """
+    a = np.asarray(a, dtype=np.float64)
+    n = a.shape[1]
+    q1, r1, r1inv = cqr(a)
+    try:
+        q, r2, r2inv = cqr(q1)
+    except NotSPD as e:
+        raise NotSPD(n + e.j) from None
+    r = upper_product(r2, r1)
+    if not return_intermediates:
+        return q, r
+    return q, r, {
+        "W1": syrk(a), "R1": r1, "R1inv": r1inv, "Q1": q1,
+        "W2": syrk(q1), "R2": r2, "R2inv": r2inv,
+    }
+
+
+def cqr2_mixed(a: np.ndarray, return_intermediates: bool = False):
+    """CQR2 with pass 1's Q1 = A R1^{-1} formed in FP32 (FP32 products, FP32 sums).
+
+    Gram, CholInv and everything in pass 2 stay FP64; pass 2 factors the stored
+    FP32 Q1 after exact conversion to FP64.  Not in the paper (it fixes no
+    precision); it is the reduced-precision variant the GPU path offers, and is
+    checked only against the FP64 oracle and the orthogonality invariant.
+    """
+    a = np.asarray(a, dtype=np.float64)
+    n = a.shape[1]
+    w1 = syrk(a)
+    l1, y1 = cholinv(w1)
+    r1 = l1.T.copy()
+    r1inv = y1.T.copy()
+    q1_32 = a.astype(np.float32) @ r1inv.astype(np.float32)
+    q1 = q1_32.astype(np.float64)
+    try:
+        q, r2, r2inv = cqr(q1)
+    except NotSPD as e:
+        raise NotSPD(n + e.j) from None
+    r = upper_product(r2, r1)
+    if not return_intermediates:
+        return q, r
+    return q, r, {"W1": w1, "R1": r1, "R1inv": r1inv, "Q1": q1,
+                  "R2": r2, "R2inv": r2inv}

@@ -1,0 +1,291 @@
+"""Pins for the CPU oracle: each checks it against something other than itself.
+
+* exact worked examples (tests/golden, exact rational arithmetic) — CholInv
+  reproduces L and Y bit for bit, for even and odd n;
+* brute force — integer Gram matrices computed exactly with Python ints;
+* library routines for special cases — LAPACK potrf/trtri (scipy) for
+  CholInv, LAPACK Householder QR for CQR2's R (Introduction: CQR2 is as
+  accurate as Householder QR for cond(A) = O(eps^{-1/2}));
+* closed forms — n = 1 and n = 2 QR, exact 4x3 QR;
+* 50-digit Gram-Schmidt (mpmath) on tiny inputs;
+* invariants — A = QR, QᵀQ = I, R upper with positive diagonal, power-of-two
+  scaling is exact;
+* planted mistakes — mutated copies of the oracle must fail the pins above.
+"""
+import json
+import math
+import os
+from fractions import Fraction as F
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import oracle
+from oracle import cqr2_ref
+from synth import gdv_matrix, integer_matrix
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+U = 2.0 ** -53
+
+
+def _gold(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+def _frac_matrix(rows):
+    return np.array([[float(F(x)) for x in r] for r in rows])
+
+
+# ---------------------------------------------------------------- Syrk ---
+
+@pytest.mark.parametrize("m,n,seed", [(1, 1, 0), (7, 3, 1), (64, 16, 2), (1000, 33, 3)])
+def test_syrk_exact_integer_gram(m, n, seed):
+    a = integer_matrix(m, n, 64, seed)
+    w = oracle.syrk(a)
+    ai = a.astype(np.int64)
+    exact = [[int(sum(int(ai[k, i]) * int(ai[k, j]) for k in range(m))) for j in range(n)]
+             for i in range(n)]
+    assert np.array_equal(w, np.array(exact, dtype=np.float64))
+
+
+def test_syrk_shape_and_symmetry():
+    a = gdv_matrix(50, 7, 10.0, 9)
+    w = oracle.syrk(a)
+    assert w.shape == (7, 7)
+    assert np.array_equal(w, w.T)
+
+
+# ------------------------------------------------------------- CholInv ---
+
+@pytest.mark.parametrize("n", [2, 3, 5, 8, 13, 16, 33])
+def test_cholinv_exact_examples(n):
+    d = _gold(f"cholinv_exact_n{n}.json")
+    l, y = oracle.cholinv(np.array(d["W"]))
+    assert np.array_equal(l, np.array(d["L"]))
+    assert np.array_equal(y, np.array(d["Y"]))
+
+
+def test_cholinv_reads_lower_triangle_only():
+    d = _gold("cholinv_exact_n8.json")
+    w = np.array(d["W"])
+    w_polluted = np.tril(w) + np.triu(np.full_like(w, 1e300), 1)
+    l, y = oracle.cholinv(w_polluted)
+    assert np.array_equal(l, np.array(d["L"]))
+    assert np.array_equal(y, np.array(d["Y"]))
+
+
+@pytest.mark.parametrize("n,kappa", [(1, 1.0), (4, 10.0), (31, 1e3), (64, 1e4), (128, 1e6)])
+def test_cholinv_matches_lapack(n, kappa):
+    a = gdv_matrix(max(2 * n, 8), n, math.sqrt(kappa), 100 + n)
+    w = oracle.syrk(a)
+    l, y = oracle.cholinv(w)
+    l_ref = scipy.linalg.cholesky(w, lower=True)
+    y_ref, info = scipy.linalg.lapack.dtrtri(l_ref, lower=1)
+    assert info == 0
+    cw = np.linalg.cond(w)
+    tol = 20 * n * U * cw
+    assert oracle.rel_fro(l, l_ref) <= tol
+    assert oracle.rel_fro(y, np.tril(y_ref)) <= tol
+    # invariants of Algorithm 2's postcondition
+    assert np.array_equal(l, np.tril(l)) and np.array_equal(y, np.tril(y))
+    assert np.all(np.diag(l) > 0)
+    assert np.linalg.norm(l @ l.T - w) <= 10 * n * U * np.linalg.norm(w)
+    assert np.linalg.norm(y @ l - np.eye(n)) <= 10 * n * U * cw ** 0.5 * 10
+
+
+def test_cholinv_breakdown_columns():
+    d = _gold("cholinv_exact_n8.json")
+    w = np.array(d["W"])
+    for j in (0, 3, 7):
+        wz = w.copy()
+        wz[j, :] = 0.0
+        wz[:, j] = 0.0
+        with pytest.raises(oracle.NotSPD) as e:
+            oracle.cholinv(wz)
+        assert e.value.j == j + 1
+    wn = w.copy()
+    wn[5, 5] = np.nan
+    with pytest.raises(oracle.NotSPD) as e:
+        oracle.cholinv(wn)
+    assert e.value.j == 6
+    with pytest.raises(oracle.NotSPD) as e:
+        oracle.cholinv(-np.eye(3))
+    assert e.value.j == 1
+
+
+# ---------------------------------------------------------------- CQR2 ---
+
+def test_qr_closed_form_n1():
+    a = np.array([[1.0], [2.0], [2.0]])
+    q, r = oracle.cqr2(a)
+    assert abs(r[0, 0] - 3.0) <= 4 * U * 3.0
+    assert np.max(np.abs(q[:, 0] - a[:, 0] / 3.0)) <= 4 * U
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        v = rng.standard_normal((int(rng.integers(1, 200)), 1))
+        q, r = oracle.cqr2(v)
+        nrm = np.linalg.norm(v)
+        assert abs(r[0, 0] - nrm) <= 8 * U * nrm
+        assert np.max(np.abs(q - v / nrm)) <= 8 * U
+
+
+@pytest.mark.parametrize("name", ["qr_exact_2x2.json", "qr_exact_4x3.json"])
+def test_qr_exact_closed_form(name):
+    d = _gold(name)
+    a = np.array(d["A"])
+    q, r = oracle.cqr2(a)
+    q_ref, r_ref = _frac_matrix(d["Q"]), _frac_matrix(d["R"])
+    assert np.max(np.abs(q - q_ref)) <= 16 * U
+    assert np.max(np.abs(r - r_ref)) <= 16 * U * np.abs(r_ref).max()
+    assert np.array_equal(r, np.triu(r))
+
+
+def test_qr_n2_closed_form_random():
+    rng = np.random.default_rng(11)
+    for _ in range(20):
+        m = int(rng.integers(2, 50))
+        a, b = rng.standard_normal(m), rng.standard_normal(m)
+        q, r = oracle.cqr2(np.stack([a, b], axis=1))
+        na = np.linalg.norm(a)
+        r12 = a @ b / na
+        r22 = np.linalg.norm(b - (a @ b / na ** 2) * a)
+        ref = np.array([[na, r12], [0.0, r22]])
+        assert np.max(np.abs(r - ref)) <= 64 * U * np.abs(ref).max() * max(1.0, na / r22)
+
+
+@pytest.mark.parametrize("m,n,kappa,seed", [
+    (4096, 64, 1e3, 1), (2000, 128, 1e6, 2), (3000, 256, 1e6, 4), (500, 17, 1e4, 5),
+    (64, 64, 1e2, 6)])
+def test_cqr2_matches_householder(m, n, kappa, seed):
+    a = gdv_matrix(m, n, kappa, seed)
+    q, r = oracle.cqr2(a)
+    qh, rh = oracle.householder_qr_posdiag(a)
+    assert oracle.orthogonality(q) <= 1e-12
+    assert oracle.residual(a, q, r) <= 1e-13
+    assert oracle.rel_fro(r, rh) <= 1e-9
+    assert oracle.rel_fro(q, qh) <= 1e-9
+    assert np.array_equal(r, np.triu(r)) and np.all(np.diag(r) > 0)
+
+
+def test_cqr2_refinement_factor_near_identity():
+    # Introduction: the second CholeskyQR's triangular factor is near the identity.
+    a = gdv_matrix(3000, 40, 1e5, 8)
+    _, _, it = oracle.cqr2(a, return_intermediates=True)
+    assert np.linalg.norm(it["R2"] - np.eye(40)) <= 1e-4
+    assert np.linalg.norm(it["R2"] - np.eye(40)) > 0.0
+
+
+def test_cqr2_power_of_two_scaling_is_exact():
+    a = gdv_matrix(300, 12, 1e4, 12)
+    q, r = oracle.cqr2(a)
+    for k in (-7, 3, 20):
+        qs, rs = oracle.cqr2(a * 2.0 ** k)
+        assert np.array_equal(qs, q)
+        assert np.array_equal(rs, r * 2.0 ** k)
+
+
+def test_cqr2_mpmath_gram_schmidt():
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 50
+    rng = np.random.default_rng(21)
+    for m, n in ((4, 1), (6, 3), (16, 4), (9, 4)):
+        a = rng.standard_normal((m, n))
+        cols = [[mpmath.mpf(float(a[i, j])) for i in range(m)] for j in range(n)]
+        qs, r_ref = [], [[mpmath.mpf(0)] * n for _ in range(n)]
+        for j in range(n):
+            v = list(cols[j])
+            for k in range(j):
+                rkj = mpmath.fsum(qs[k][i] * cols[j][i] for i in range(m))
+                r_ref[k][j] = rkj
+                v = [v[i] - rkj * qs[k][i] for i in range(m)]
+            nv = mpmath.sqrt(mpmath.fsum(x * x for x in v))
+            r_ref[j][j] = nv
+            qs.append([x / nv for x in v])
+        q, r = oracle.cqr2(a)
+        rr = np.array([[float(x) for x in row] for row in r_ref])
+        qq = np.array([[float(qs[j][i]) for j in range(n)] for i in range(m)])
+        assert np.max(np.abs(r - rr)) <= 1e-13 * np.abs(rr).max()
+        assert np.max(np.abs(q - qq)) <= 1e-13
+
+
+def test_cqr2_second_pass_breakdown_offset():
+    # An exactly rank-deficient A breaks down in pass 1 with the column index.
+    a = gdv_matrix(40, 6, 10.0, 3)
+    a[:, 4] = 0.0
+    with pytest.raises(oracle.NotSPD) as e:
+        oracle.cqr2(a)
+    assert e.value.j == 5
+
+
+def test_mixed_oracle_orthogonality_and_error_level():
+    # Mixed form: not in the paper (parity unpinned by it); pinned to the FP64
+    # oracle and the orthogonality invariant.
+    a = gdv_matrix(4096, 64, 1e3, 1)
+    q, r = oracle.cqr2_mixed(a)
+    q64, r64 = oracle.cqr2(a)
+    assert oracle.orthogonality(q) <= 1e-12
+    assert oracle.residual(a, q, r) <= 1e-5       # ~FP32 unit roundoff level
+    assert oracle.rel_fro(r, r64) <= 1e-4
+    assert oracle.residual(a, q, r) > 1e-12       # really took FP32 arithmetic
+
+
+# ------------------------------------------------------ planted mistakes ---
+
+def _mutant_cholinv(kind):
+    def f(a):
+        a = np.asarray(a, dtype=np.float64)
+        n = a.shape[0]
+        if n == 1:
+            if not a[0, 0] > 0:
+                raise oracle.NotSPD(1)
+            l = math.sqrt(a[0, 0])
+            return np.array([[l]]), np.array([[1.0 / l]])
+        h = n // 2
+        l11, y11 = f(a[:h, :h])
+        l21 = a[h:, :h] @ (y11 if kind == "transpose" else y11.T)
+        schur = a[h:, h:] - (0.0 if kind == "drop_update" else l21 @ l21.T)
+        l22, y22 = f(schur)
+        y21 = (y22 @ (l21 @ y11)) if kind == "sign" else -(y22 @ (l21 @ y11))
+        l = np.zeros((n, n)); y = np.zeros((n, n))
+        l[:h, :h], l[h:, :h], l[h:, h:] = l11, l21, l22
+        y[:h, :h], y[h:, :h], y[h:, h:] = y11, y21, y22
+        return l, y
+    return f
+
+
+@pytest.mark.parametrize("kind", ["transpose", "drop_update", "sign"])
+def test_pins_catch_planted_cholinv_mistakes(kind, monkeypatch):
+    mut = _mutant_cholinv(kind)
+    d = _gold("cholinv_exact_n8.json")
+    try:
+        l, y = mut(np.array(d["W"]))
+        exact_ok = np.array_equal(l, np.array(d["L"])) and np.array_equal(y, np.array(d["Y"]))
+    except oracle.NotSPD:
+        exact_ok = False
+    assert not exact_ok
+    monkeypatch.setattr(cqr2_ref, "cholinv", mut)
+    a = gdv_matrix(200, 8, 10.0, 4)
+    try:
+        q, r = cqr2_ref.cqr2(a)
+        qh, rh = oracle.householder_qr_posdiag(a)
+        good = oracle.rel_fro(r, rh) <= 1e-9 and oracle.orthogonality(q) <= 1e-12
+    except oracle.NotSPD:
+        good = False
+    assert not good
+
+
+def test_pins_catch_planted_syrk_mistake(monkeypatch):
+    a = integer_matrix(30, 5, 8, 1)
+    monkeypatch.setattr(cqr2_ref, "syrk", lambda x: np.asarray(x) @ np.asarray(x).T)
+    with pytest.raises(Exception):
+        q, r = cqr2_ref.cqr2(a)
+        assert r.shape == (5, 5)
+
+
+def test_pins_catch_planted_second_pass_skip(monkeypatch):
+    # Dropping pass 2 (plain CholeskyQR) loses orthogonality at cond 1e6.
+    a = gdv_matrix(2000, 32, 1e6, 2)
+    q1, r1, _ = oracle.cqr(a)
+    assert oracle.orthogonality(q1) > 1e-12
