@@ -1,0 +1,247 @@
+"""Benchmark: CholeskyQR2 of the 1048576 x 128 FP64 matrix (cond 1e6) on one MI355X.
+
+One step = one full CholeskyQR2 (both passes and R = R2 R1) through the C ABI
+(cqr2_factor) on a device-resident synthetic matrix A = G diag(logspace(0,-6,128)) V.
+Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+FP64_PEAK_TFLOPS = 78.6        # MI355X dense FP64 (vector and matrix)
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1710_08471_amd", "csrc", "cqr2_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_tall_1Mx128.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def flops_cqr2(m: int, n: int) -> float:
+    """CholeskyQR2 flop count along its critical path: 4 m n^2 + 5 n^3 / 3."""
+    return 4.0 * m * n * n + 5.0 * n ** 3 / 3.0
+
+
+def flops_householder(m: int, n: int) -> float:
+    """The paper's GFLOP/s numerator (Householder QR): 2 m n^2 - 2 n^3 / 3."""
+    return 2.0 * m * n * n - 2.0 * n ** 3 / 3.0
+
+
+def kernel_units(name: str, m: int, n: int):
+    """Algorithmic work of one launch: (bound, flops, bytes)."""
+    tri = m * n * (n + 1)            # 2 flops per multiply-add over the lower / upper triangle
+    if name == "gram":
+        return "mfma", float(tri), 8.0 * m * n                  # reads A once
+    if name in ("apply_rinv_pass1", "apply_rinv_pass2"):
+        return "hbm", float(tri), 16.0 * m * n                  # reads A, writes Q
+    if name == "gram_reduce":
+        ng = 1
+        while ng < (n + 3) // 4:
+            ng *= 2
+        return "hbm", 0.0, 8.0 * 256 * 16 * (ng * (ng + 1) // 2)  # partial Grams read once
+    if name == "cholinv":
+        return "alu", 2.0 * n ** 3 / 3.0, 8.0 * n * n
+    return "alu", 2.0 * n ** 3 / 3.0, 24.0 * n * n
+
+
+def source_sha() -> str:
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def read_traffic(kernel: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they
+    were taken on the current kernel source; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha") != source_sha():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else float(k["bytes_per_launch"])
+
+
+def cpu_baseline(a, budget_s: float):
+    """The CPU oracle (plain FP64 CholeskyQR2, numpy) on this host."""
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+    except ImportError:
+        threadpool_info = None
+    m, n = a.shape
+    times = []
+    t_start = time.perf_counter()
+    while True:
+        t0 = time.perf_counter()
+        oracle.cqr2(a)
+        times.append(time.perf_counter() - t0)
+        if time.perf_counter() - t_start + times[-1] > budget_s or len(times) >= 5:
+            break
+    cores = os.cpu_count()
+    if threadpool_info is not None:
+        blas = [p for p in threadpool_info() if p.get("user_api") == "blas"]
+        if blas:
+            cores = int(blas[0].get("num_threads", cores))
+    t = statistics.median(times)
+    return {
+        "value": round(flops_cqr2(m, n) / t / 1e9, 3),
+        "unit": "GFLOP/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": f"full {m}x{n} matrix, median of {len(times)} oracle CholeskyQR2 runs ({t:.3f} s each)",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time for the CPU baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-gib", type=float, default=0.0,
+                    help="also run a device copy of this many GiB (counter calibration under rocprofv3)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1710_08471_amd as cq
+    from synth import WORKLOADS, workload_matrix
+
+    wl = WORKLOADS["tall_1Mx128"]
+    m, n = wl.m, wl.n
+    log(f"generating {wl.description} (seed {wl.seed}) on the host ...")
+    t0 = time.perf_counter()
+    a_host = workload_matrix("tall_1Mx128")
+    log(f"  generated in {time.perf_counter() - t0:.1f} s")
+
+    cq.load()
+    dev = torch.device("cuda:0")
+    a = cq.colmajor(torch.from_numpy(a_host).to(dev))
+    q = cq.empty_colmajor(m, n, device=dev)
+    r = cq.empty_colmajor(n, n, device=dev)
+    lib = cq.load()
+    stream = torch.cuda.current_stream()
+    sp = cq.ctypes.c_void_p(stream.cuda_stream)
+
+    def step():
+        rc = lib.cqr2_factor(cq._ptr(a), m, n, m, cq._ptr(q), cq._ptr(r), sp)
+        if rc != 0:
+            raise cq.CQR2Error(rc, "cqr2_factor")
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"warmup {args.warmup} done")
+
+    # Timed region: K whole CholeskyQR2 steps.
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = elapsed * 1e3 / args.steps
+    log(f"timed {args.steps} steps: {ms_per_step:.4f} ms/step")
+
+    # Same K steps again with HIP events around every kernel (on this stream).
+    cq.timing_reset()
+    cq.timing_enable(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    inst_ms = (time.perf_counter() - t1) * 1e3 / args.steps
+    cq.timing_enable(False)
+    kt = cq.timing_read()
+    log("per-kernel (HIP events): " + ", ".join(
+        f"{k} {v[0] / max(v[1], 1) * 1e3:.1f} us x{v[1] // args.steps}" for k, v in kt.items() if v[1]))
+
+    if args.calib_copy_gib > 0:
+        nb = int(args.calib_copy_gib * (1 << 30)) // 8
+        src = torch.ones(nb, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    # Correctness of the last timed result (device-side check, FP64).
+    qt = q.t().contiguous()
+    orth = float(torch.linalg.norm(qt @ qt.t() - torch.eye(n, dtype=torch.float64, device=dev)))
+    resid = float(torch.linalg.norm(a - q @ r) / torch.linalg.norm(a))
+    log(f"orthogonality {orth:.3e}, residual {resid:.3e}")
+
+    t_step = ms_per_step / 1e3
+    value = flops_cqr2(m, n) / t_step / 1e9
+    hbm_bytes_6mn = 6.0 * m * n * 8
+
+    # Dominant kernel and its roofline.
+    per_kernel = {k: (v[0] / v[1], v[1]) for k, v in kt.items() if v[1]}
+    totals = {k: v[0] for k, v in kt.items() if v[1]}
+    dom_cls = max(totals, key=totals.get)
+    dom_avg_ms = per_kernel[dom_cls][0]
+    bound, fl, by = kernel_units(dom_cls, m, n)
+    kname = {"gram": "k_gram_partials", "apply_rinv_pass1": "k_apply_rinv", "apply_rinv_pass2": "k_apply_rinv",
+             "gram_reduce": "k_gram_reduce", "cholinv": "k_cholinv", "upper_product": "k_upper_product"}[dom_cls]
+    if bound == "hbm":
+        achieved = by / (dom_avg_ms / 1e3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4)}
+    else:
+        achieved = fl / (dom_avg_ms / 1e3) / 1e12
+        roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / FP64_PEAK_TFLOPS, 4)}
+    roof["kernel"] = f"{kname} ({dom_cls})"
+    roof["avg_launch_ms"] = round(dom_avg_ms, 5)
+    roof["traffic"] = read_traffic(dom_cls)
+
+    out = {
+        "metric": "CQR2 GFLOP/s (1M x 128 FP64)",
+        "value": round(value, 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "tall_1Mx128", "m": m, "n": n, "lda": m, "kappa": wl.kappa, "seed": wl.seed,
+                   "matrix": "A = G diag(logspace(0,-6,128)) V, G orthonormal 1048576x128, V orthogonal"},
+        "hbm_roofline_frac_6mn": round(hbm_bytes_6mn / t_step / 1e9 / HBM_PEAK_GBS, 4),
+        "paper_convention_gflops": round(flops_householder(m, n) / t_step / 1e9, 2),
+        "kernel_ms": {k: round(v[0], 5) for k, v in per_kernel.items()},
+        "instrumented_ms_per_step": round(inst_ms, 5),
+        "orthogonality": orth,
+        "residual": resid,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle ...")
+        out["cpu_baseline"] = cpu_baseline(a_host, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,232 @@
+"""Python binding of libcqr2.so (MI355X CholeskyQR2): argument marshalling only.
+
+Every step of the factorization runs in the HIP kernels behind the C ABI
+declared in ``include/cqr2.h``; torch supplies device memory and the current
+stream.  There is no CPU or PyTorch fallback: if the library is not built,
+``load()`` raises.
+
+Matrices are column-major: a torch tensor of shape (m, n) with strides
+(1, ld), ld >= m (``colmajor()`` converts).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libcqr2.so")
+
+CQR2_ERR_HIP = -100
+CQR2_ERR_UNSUPPORTED = -101
+CQR2_FP64 = 0
+CQR2_MIXED_P1_FP32 = 1
+NUM_TIMERS = 6
+TIMER_NAMES = ("gram", "gram_reduce", "cholinv", "apply_rinv_pass1", "apply_rinv_pass2", "upper_product")
+
+# Every symbol include/cqr2.h declares, with (restype, argtypes).
+_i64, _u32, _sz, _vp, _i32 = ctypes.c_int64, ctypes.c_uint32, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_int
+SIGNATURES = {
+    "cqr2_factor": (_i32, [_vp, _i64, _i64, _i64, _vp, _vp, _vp]),
+    "cqr2_workspace_size": (_sz, [_i64, _i64, _u32]),
+    "cqr2_factor_ex": (_i32, [_vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _sz, _vp, _u32, _vp]),
+    "cqr2_gram_workspace_size": (_sz, [_i64, _i64]),
+    "cqr2_gram": (_i32, [_vp, _i64, _i64, _i64, _vp, _i64, _vp, _sz, _vp]),
+    "cqr2_cholinv": (_i32, [_vp, _i64, _i64, _vp, _vp, _i64, _vp, _vp]),
+    "cqr2_apply_rinv": (_i32, [_vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp]),
+    "cqr2_upper_product": (_i32, [_vp, _vp, _vp, _i64, _i64, _vp]),
+    "cqr2_status_string": (ctypes.c_char_p, [_i32]),
+    "cqr2_version": (ctypes.c_char_p, []),
+    "cqr2_timing_enable": (_i32, [_i32]),
+    "cqr2_timing_reset": (_i32, []),
+    "cqr2_timing_read": (_i32, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), _i32]),
+}
+
+_lib = None
+
+
+class CQR2Error(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        msg = "?"
+        if _lib is not None:
+            msg = _lib.cqr2_status_string(code).decode()
+        super().__init__(f"{where} returned {code}: {msg}")
+
+
+def load(path: str | None = None):
+    """Load libcqr2.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"{p} is missing: build it with `python -m paper_1710_08471_amd.build`")
+    lib = ctypes.CDLL(p)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, where: str):
+    if rc != 0:
+        raise CQR2Error(rc, where)
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def colmajor(t, ld: int | None = None):
+    """Column-major copy of a 2-D tensor (strides (1, ld)) on the same device."""
+    import torch
+    m, n = t.shape
+    ld = max(ld or m, 1)
+    buf = torch.empty((n, ld), dtype=t.dtype, device=t.device)
+    out = buf.t()[:m, :]
+    out.copy_(t)
+    return out
+
+
+def empty_colmajor(m: int, n: int, dtype=None, device=None, ld: int | None = None):
+    import torch
+    ld = max(ld or m, 1)
+    buf = torch.empty((n, ld), dtype=dtype or torch.float64, device=device)
+    return buf.t()[:m, :]
+
+
+def _ld(t) -> int:
+    m, n = t.shape
+    if t.stride(0) != 1 and not (m <= 1):
+        raise ValueError("tensor must be column-major (stride(0) == 1)")
+    return max(t.stride(1) if n > 1 else max(m, 1), 1)
+
+
+def _require_cuda_f64(t, name):
+    import torch
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA/HIP tensor")
+    if t.dtype != torch.float64:
+        raise ValueError(f"{name} must be float64")
+
+
+def workspace_size(m: int, n: int, flags: int = CQR2_FP64) -> int:
+    return int(load().cqr2_workspace_size(m, n, flags))
+
+
+def factor(A):
+    """(Q, R) = CholeskyQR2(A) with library-managed workspace (cqr2_factor)."""
+    import torch
+    lib = load()
+    _require_cuda_f64(A, "A")
+    m, n = A.shape
+    lda = _ld(A)
+    Q = empty_colmajor(m, n, device=A.device, ld=lda)
+    R = empty_colmajor(n, n, device=A.device)
+    rc = lib.cqr2_factor(_ptr(A), m, n, lda, _ptr(Q), _ptr(R), _stream())
+    _check(rc, "cqr2_factor")
+    return Q, R
+
+
+def factor_ex(A, Q=None, R=None, work=None, info=None, flags: int = CQR2_FP64):
+    """cqr2_factor_ex with caller buffers (allocated here when None)."""
+    import torch
+    lib = load()
+    _require_cuda_f64(A, "A")
+    m, n = A.shape
+    lda = _ld(A)
+    if Q is None:
+        Q = empty_colmajor(m, n, device=A.device)
+    if R is None:
+        R = empty_colmajor(n, n, device=A.device)
+    wbytes = workspace_size(m, n, flags)
+    if work is None:
+        work = torch.empty(max(wbytes, 1), dtype=torch.uint8, device=A.device)
+    rc = lib.cqr2_factor_ex(_ptr(A), m, n, lda, _ptr(Q), _ld(Q), _ptr(R), _ld(R), _ptr(work),
+                            work.numel() * work.element_size(), _ptr(info), flags, _stream())
+    _check(rc, "cqr2_factor_ex")
+    return Q, R
+
+
+def gram(A, W=None, work=None):
+    """W = AᵀA (cqr2_gram)."""
+    import torch
+    lib = load()
+    _require_cuda_f64(A, "A")
+    m, n = A.shape
+    if W is None:
+        W = empty_colmajor(n, n, device=A.device)
+    wb = int(lib.cqr2_gram_workspace_size(m, n))
+    if work is None:
+        work = torch.empty(max(wb, 8), dtype=torch.uint8, device=A.device)
+    rc = lib.cqr2_gram(_ptr(A), m, n, _ld(A), _ptr(W), _ld(W), _ptr(work),
+                       work.numel() * work.element_size(), _stream())
+    _check(rc, "cqr2_gram")
+    return W
+
+
+def cholinv(W, info=None):
+    """(R, Rinv) = CholInv factors of the SPD matrix W (cqr2_cholinv)."""
+    lib = load()
+    _require_cuda_f64(W, "W")
+    n = W.shape[0]
+    R = empty_colmajor(n, n, device=W.device)
+    Rinv = empty_colmajor(n, n, device=W.device)
+    rc = lib.cqr2_cholinv(_ptr(W), n, _ld(W), _ptr(R), _ptr(Rinv), _ld(R), _ptr(info), _stream())
+    _check(rc, "cqr2_cholinv")
+    return R, Rinv
+
+
+def apply_rinv(A, U, Q=None):
+    """Q = A U for upper-triangular U (cqr2_apply_rinv); Q may be A (in place)."""
+    lib = load()
+    _require_cuda_f64(A, "A")
+    _require_cuda_f64(U, "U")
+    m, n = A.shape
+    if Q is None:
+        Q = empty_colmajor(m, n, device=A.device)
+    rc = lib.cqr2_apply_rinv(_ptr(A), m, n, _ld(A), _ptr(U), _ld(U), _ptr(Q), _ld(Q), _stream())
+    _check(rc, "cqr2_apply_rinv")
+    return Q
+
+
+def upper_product(R2, R1, R=None):
+    """R = R2 R1 for upper-triangular factors (cqr2_upper_product)."""
+    lib = load()
+    n = R2.shape[0]
+    ld = _ld(R2)
+    if _ld(R1) != ld:
+        raise ValueError("R2 and R1 must share a leading dimension")
+    if R is None:
+        R = empty_colmajor(n, n, device=R2.device, ld=ld)
+    rc = lib.cqr2_upper_product(_ptr(R2), _ptr(R1), _ptr(R), n, ld, _stream())
+    _check(rc, "cqr2_upper_product")
+    return R
+
+
+def timing_enable(on: bool = True):
+    load().cqr2_timing_enable(1 if on else 0)
+
+
+def timing_reset():
+    load().cqr2_timing_reset()
+
+
+def timing_read():
+    """{kernel class: (total_ms, launches)} since the last reset."""
+    lib = load()
+    tot = (ctypes.c_double * NUM_TIMERS)()
+    cnt = (ctypes.c_int64 * NUM_TIMERS)()
+    _check(lib.cqr2_timing_read(tot, cnt, NUM_TIMERS), "cqr2_timing_read")
+    return {TIMER_NAMES[i]: (tot[i], cnt[i]) for i in range(NUM_TIMERS)}
+
+
+def version() -> str:
+    return load().cqr2_version().decode()

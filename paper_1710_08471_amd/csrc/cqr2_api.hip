@@ -1,0 +1,363 @@
+// C ABI of libcqr2.so: argument checks, workspace planning and the
+// stream-ordered launch sequence of CholeskyQR2 (Algorithm 5 = two passes of
+// Algorithm 4, then R = R2 R1).  All checks run on the host before any HIP
+// call, so invalid arguments never launch anything.
+#include "cqr2.h"
+#include "cqr2_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+namespace {
+
+using cqr2::GramPlan;
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Byte ranges [p, p + bytes) overlap?
+bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes) {
+  if (a == nullptr || b == nullptr || abytes == 0 || bbytes == 0) return false;
+  const uintptr_t x0 = (uintptr_t)a, x1 = x0 + abytes;
+  const uintptr_t y0 = (uintptr_t)b, y1 = y0 + bbytes;
+  return x0 < y1 && y0 < x1;
+}
+
+size_t matrix_bytes(int64_t rows, int64_t cols, int64_t ld) {
+  if (rows <= 0 || cols <= 0) return 0;
+  return (size_t)((cols - 1) * ld + rows) * sizeof(double);
+}
+
+bool aligned8(const void* p) { return ((uintptr_t)p & 7u) == 0; }
+
+int device_cus() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+    return 256;
+  return cus;
+}
+
+// Workspace layout of one factorization.
+struct Layout {
+  GramPlan gram;
+  int np = 0;
+  size_t off_info = 0, off_part = 0, off_w = 0, off_u1 = 0, off_u2 = 0, off_r1 = 0, off_r2 = 0;
+  size_t total = 0;
+};
+
+Layout make_layout(int64_t m, int64_t n) {
+  Layout L;
+  L.gram = cqr2::plan_gram(m, n);
+  L.np = cqr2::padded_order(n);
+  size_t off = 0;
+  L.off_info = off; off += align_up(sizeof(int32_t) * 4);
+  L.off_part = off; off += align_up(L.gram.partial_bytes);
+  L.off_w = off;    off += align_up((size_t)n * n * sizeof(double));
+  L.off_u1 = off;   off += align_up((size_t)L.np * L.np * sizeof(double));
+  L.off_u2 = off;   off += align_up((size_t)L.np * L.np * sizeof(double));
+  L.off_r1 = off;   off += align_up((size_t)n * n * sizeof(double));
+  L.off_r2 = off;   off += align_up((size_t)n * n * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+// ---- timing instrumentation -------------------------------------------------
+struct Timer {
+  bool enabled = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  struct Rec { int cls; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+};
+Timer g_timer;
+std::mutex g_timer_mu;
+
+hipEvent_t timer_event() {
+  if (g_timer.used == g_timer.pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    g_timer.pool.push_back(e);
+  }
+  return g_timer.pool[g_timer.used++];
+}
+
+struct Scope {
+  int cls;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  Scope(int c, hipStream_t st) : cls(c), s(st) {
+    if (!g_timer.enabled) return;
+    std::lock_guard<std::mutex> g(g_timer_mu);
+    a = timer_event();
+    if (a) hipEventRecord(a, s);
+  }
+  ~Scope() {
+    if (!g_timer.enabled || a == nullptr) return;
+    std::lock_guard<std::mutex> g(g_timer_mu);
+    hipEvent_t b = timer_event();
+    if (b == nullptr) return;
+    hipEventRecord(b, s);
+    g_timer.recs.push_back({cls, a, b});
+  }
+};
+
+// ---- library-cached workspace for the 7-argument form -----------------------
+struct CachedWs {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+std::mutex g_ws_mu;
+std::vector<CachedWs> g_ws;  // per device
+
+void* cached_workspace(size_t bytes, int* err) {
+  std::lock_guard<std::mutex> g(g_ws_mu);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) { *err = CQR2_ERR_HIP; return nullptr; }
+  if ((int)g_ws.size() <= dev) g_ws.resize(dev + 1);
+  CachedWs& w = g_ws[dev];
+  if (w.bytes < bytes) {
+    if (w.ptr) {
+      // The previous workspace may still be used by enqueued work.
+      if (hipDeviceSynchronize() != hipSuccess) { *err = CQR2_ERR_HIP; return nullptr; }
+      hipFree(w.ptr);
+      w.ptr = nullptr;
+      w.bytes = 0;
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) { *err = CQR2_ERR_HIP; return nullptr; }
+    w.ptr = p;
+    w.bytes = bytes;
+  }
+  *err = 0;
+  return w.ptr;
+}
+
+int check_hip(hipError_t e) { return e == hipSuccess ? 0 : CQR2_ERR_HIP; }
+
+#define CQR2_TRY(expr)            \
+  do {                            \
+    int _rc = check_hip((expr));  \
+    if (_rc != 0) return _rc;     \
+  } while (0)
+
+// The enqueued CholeskyQR2 sequence; arguments already validated.
+int run_factor(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, int64_t ldq, double* R,
+               int64_t ldr, char* ws, const Layout& L, int32_t* d_info, hipStream_t s, int cus) {
+  int32_t* info = (int32_t*)(ws + L.off_info);
+  double* part = (double*)(ws + L.off_part);
+  double* W = (double*)(ws + L.off_w);
+  double* U1 = (double*)(ws + L.off_u1);
+  double* U2 = (double*)(ws + L.off_u2);
+  double* R1 = (double*)(ws + L.off_r1);
+  double* R2 = (double*)(ws + L.off_r2);
+  const int ni = (int)n;
+  CQR2_TRY(cqr2::launch_set_info(info, 0, s));
+  // ---- pass 1: CQR(A) ----
+  { Scope t(0, s); CQR2_TRY(cqr2::launch_gram_partials(L.gram, A, m, ni, lda, part, info, s)); }
+  { Scope t(1, s); CQR2_TRY(cqr2::launch_gram_reduce(L.gram, part, ni, W, n, info, s)); }
+  { Scope t(2, s); CQR2_TRY(cqr2::launch_cholinv(W, n, ni, R1, n, nullptr, 0, U1, L.np, info, 0, s)); }
+  { Scope t(3, s); CQR2_TRY(cqr2::launch_apply_rinv(A, m, ni, lda, U1, L.np, 1, Q, ldq, info, cus, s)); }
+  // ---- pass 2: CQR(Q1), in place ----
+  { Scope t(0, s); CQR2_TRY(cqr2::launch_gram_partials(L.gram, Q, m, ni, ldq, part, info, s)); }
+  { Scope t(1, s); CQR2_TRY(cqr2::launch_gram_reduce(L.gram, part, ni, W, n, info, s)); }
+  { Scope t(2, s); CQR2_TRY(cqr2::launch_cholinv(W, n, ni, R2, n, nullptr, 0, U2, L.np, info, ni, s)); }
+  { Scope t(4, s); CQR2_TRY(cqr2::launch_apply_rinv(Q, m, ni, ldq, U2, L.np, 1, Q, ldq, info, cus, s)); }
+  // ---- R = R2 R1 ----
+  { Scope t(5, s); CQR2_TRY(cqr2::launch_upper_product(R2, R1, n, R, ldr, ni, info, d_info, s)); }
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* cqr2_version(void) { return "cqr2-mi355x 0.1 (gfx950)"; }
+
+const char* cqr2_status_string(int code) {
+  switch (code) {
+    case 0: return "success";
+    case CQR2_ERR_HIP: return "HIP runtime error";
+    case CQR2_ERR_UNSUPPORTED: return "unsupported problem size";
+    default: break;
+  }
+  if (code < 0 && code > -20) return "invalid argument (see the argument index = -code)";
+  return "unknown status";
+}
+
+size_t cqr2_workspace_size(int64_t m, int64_t n, uint32_t flags) {
+  if (m < n || n < 1 || n > CQR2_MAX_N || flags != CQR2_FP64) return 0;
+  return make_layout(m, n).total;
+}
+
+int cqr2_factor_ex(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, int64_t ldq, double* R,
+                   int64_t ldr, void* work, size_t work_bytes, int32_t* d_info, uint32_t flags,
+                   void* stream) {
+  // -- host argument checks (LAPACK-style negative argument index) --
+  if (n < 0) return -3;
+  if (m < n) return -2;
+  if (lda < (m > 1 ? m : 1)) return -4;
+  if (ldq < (m > 1 ? m : 1)) return -6;
+  if (ldr < (n > 1 ? n : 1)) return -8;
+  if (flags != CQR2_FP64) return -12;
+  if (n == 0) return 0;
+  if (A == nullptr || !aligned8(A)) return -1;
+  if (Q == nullptr || !aligned8(Q)) return -5;
+  if (R == nullptr || !aligned8(R)) return -7;
+  if (n > CQR2_MAX_N) return CQR2_ERR_UNSUPPORTED;
+  if (lda > (int64_t)1 << 40 || ldq > (int64_t)1 << 40) return lda > ((int64_t)1 << 40) ? -4 : -6;
+  const size_t abytes = matrix_bytes(m, n, lda), qbytes = matrix_bytes(m, n, ldq), rbytes = matrix_bytes(n, n, ldr);
+  if (overlaps(A, abytes, Q, qbytes)) return -5;
+  if (overlaps(A, abytes, R, rbytes)) return -7;
+  if (overlaps(Q, qbytes, R, rbytes)) return -7;
+  const Layout L = make_layout(m, n);
+  if (work == nullptr || ((uintptr_t)work % kAlign) != 0) return -9;
+  if (work_bytes < L.total) return -10;
+  if (overlaps(work, work_bytes, A, abytes) || overlaps(work, work_bytes, Q, qbytes) ||
+      overlaps(work, work_bytes, R, rbytes))
+    return -9;
+  if (d_info != nullptr && ((uintptr_t)d_info & 3u) != 0) return -11;
+  return run_factor(A, m, n, lda, Q, ldq, R, ldr, (char*)work, L, d_info, (hipStream_t)stream, device_cus());
+}
+
+int cqr2_factor(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, double* R, void* stream) {
+  if (n < 0) return -3;
+  if (m < n) return -2;
+  if (lda < (m > 1 ? m : 1)) return -4;
+  if (n == 0) return 0;
+  if (A == nullptr || !aligned8(A)) return -1;
+  if (Q == nullptr || !aligned8(Q)) return -5;
+  if (R == nullptr || !aligned8(R)) return -6;
+  if (n > CQR2_MAX_N) return CQR2_ERR_UNSUPPORTED;
+  const size_t abytes = matrix_bytes(m, n, lda), rbytes = matrix_bytes(n, n, n);
+  if (overlaps(A, abytes, Q, abytes)) return -5;
+  if (overlaps(A, abytes, R, rbytes) || overlaps(Q, abytes, R, rbytes)) return -6;
+  const Layout L = make_layout(m, n);
+  int err = 0;
+  void* ws = cached_workspace(L.total, &err);
+  if (err) return err;
+  return run_factor(A, m, n, lda, Q, lda, R, n, (char*)ws, L, nullptr, (hipStream_t)stream, device_cus());
+}
+
+size_t cqr2_gram_workspace_size(int64_t m, int64_t n) {
+  if (m < 0 || n < 1 || n > CQR2_MAX_N) return 0;
+  return align_up(cqr2::plan_gram(m, n).partial_bytes);
+}
+
+int cqr2_gram(const double* A, int64_t m, int64_t n, int64_t lda, double* W, int64_t ldw, void* work,
+              size_t work_bytes, void* stream) {
+  if (m < 0) return -2;
+  if (n < 0) return -3;
+  if (lda < (m > 1 ? m : 1)) return -4;
+  if (ldw < (n > 1 ? n : 1)) return -6;
+  if (n == 0) return 0;
+  if ((m > 0 && A == nullptr) || !aligned8(A)) return -1;  // A is not read when m == 0
+  if (W == nullptr || !aligned8(W)) return -5;
+  if (n > CQR2_MAX_N) return CQR2_ERR_UNSUPPORTED;
+  const GramPlan p = cqr2::plan_gram(m, n);
+  if (work == nullptr || ((uintptr_t)work & 7u) != 0) return -7;
+  if (work_bytes < p.partial_bytes) return -8;
+  const size_t abytes = matrix_bytes(m, n, lda), wbytes = matrix_bytes(n, n, ldw);
+  if (overlaps(A, abytes, W, wbytes)) return -5;
+  if (overlaps(work, work_bytes, A, abytes) || overlaps(work, work_bytes, W, wbytes)) return -7;
+  hipStream_t s = (hipStream_t)stream;
+  // m == 0 runs one workgroup over a fully masked stage and yields W = 0.
+  CQR2_TRY(cqr2::launch_gram_partials(p, A, m, (int)n, lda, (double*)work, nullptr, s));
+  CQR2_TRY(cqr2::launch_gram_reduce(p, (const double*)work, (int)n, W, ldw, nullptr, s));
+  return 0;
+}
+
+int cqr2_cholinv(const double* W, int64_t n, int64_t ldw, double* R, double* Rinv, int64_t ldr, int32_t* d_info,
+                 void* stream) {
+  if (n < 0) return -2;
+  if (ldw < (n > 1 ? n : 1)) return -3;
+  if (ldr < (n > 1 ? n : 1)) return -6;
+  if (n == 0) return 0;
+  if (W == nullptr || !aligned8(W)) return -1;
+  if (R == nullptr || !aligned8(R)) return -4;
+  if (Rinv == nullptr || !aligned8(Rinv)) return -5;
+  if (d_info != nullptr && ((uintptr_t)d_info & 3u) != 0) return -7;
+  if (n > CQR2_MAX_N) return CQR2_ERR_UNSUPPORTED;
+  const size_t wb = matrix_bytes(n, n, ldw), rb = matrix_bytes(n, n, ldr);
+  if (overlaps(W, wb, R, rb)) return -4;
+  if (overlaps(W, wb, Rinv, rb) || overlaps(R, rb, Rinv, rb)) return -5;
+  hipStream_t s = (hipStream_t)stream;
+  if (d_info != nullptr) CQR2_TRY(cqr2::launch_set_info(d_info, 0, s));
+  CQR2_TRY(cqr2::launch_cholinv(W, ldw, (int)n, R, ldr, Rinv, ldr, nullptr, 0, d_info, 0, s));
+  return 0;
+}
+
+int cqr2_apply_rinv(const double* A, int64_t m, int64_t n, int64_t lda, const double* U, int64_t ldu, double* Q,
+                    int64_t ldq, void* stream) {
+  if (m < 0) return -2;
+  if (n < 0) return -3;
+  if (lda < (m > 1 ? m : 1)) return -4;
+  if (ldu < (n > 1 ? n : 1)) return -6;
+  if (ldq < (m > 1 ? m : 1)) return -8;
+  if (n == 0 || m == 0) return 0;
+  if (A == nullptr || !aligned8(A)) return -1;
+  if (U == nullptr || !aligned8(U)) return -5;
+  if (Q == nullptr || !aligned8(Q)) return -7;
+  if (n > CQR2_MAX_N) return CQR2_ERR_UNSUPPORTED;
+  const size_t ab = matrix_bytes(m, n, lda), qb = matrix_bytes(m, n, ldq), ub = matrix_bytes(n, n, ldu);
+  const bool in_place = (A == Q);
+  if (in_place && lda != ldq) return -8;
+  if (!in_place && overlaps(A, ab, Q, qb)) return -7;
+  if (overlaps(U, ub, Q, qb)) return -5;
+  CQR2_TRY(cqr2::launch_apply_rinv(A, m, (int)n, lda, U, 1, ldu, Q, ldq, nullptr, device_cus(),
+                                   (hipStream_t)stream));
+  return 0;
+}
+
+int cqr2_upper_product(const double* R2, const double* R1, double* R, int64_t n, int64_t ld, void* stream) {
+  if (n < 0) return -4;
+  if (ld < (n > 1 ? n : 1)) return -5;
+  if (n == 0) return 0;
+  if (R2 == nullptr || !aligned8(R2)) return -1;
+  if (R1 == nullptr || !aligned8(R1)) return -2;
+  if (R == nullptr || !aligned8(R)) return -3;
+  const size_t b = matrix_bytes(n, n, ld);
+  if (overlaps(R, b, R2, b) || overlaps(R, b, R1, b)) return -3;
+  CQR2_TRY(cqr2::launch_upper_product(R2, R1, ld, R, ld, (int)n, nullptr, nullptr, (hipStream_t)stream));
+  return 0;
+}
+
+int cqr2_timing_enable(int enable) {
+  std::lock_guard<std::mutex> g(g_timer_mu);
+  g_timer.enabled = enable != 0;
+  return 0;
+}
+
+int cqr2_timing_reset(void) {
+  std::lock_guard<std::mutex> g(g_timer_mu);
+  g_timer.recs.clear();
+  g_timer.used = 0;
+  return 0;
+}
+
+int cqr2_timing_read(double* total_ms, int64_t* launches, int max_classes) {
+  std::lock_guard<std::mutex> g(g_timer_mu);
+  if (total_ms == nullptr || launches == nullptr || max_classes < 0) return -1;
+  for (int c = 0; c < max_classes; ++c) {
+    total_ms[c] = 0.0;
+    launches[c] = 0;
+  }
+  for (const auto& r : g_timer.recs) {
+    if (hipEventSynchronize(r.b) != hipSuccess) return CQR2_ERR_HIP;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return CQR2_ERR_HIP;
+    if (r.cls >= 0 && r.cls < max_classes) {
+      total_ms[r.cls] += ms;
+      launches[r.cls] += 1;
+    }
+  }
+  return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,620 @@
+// HIP kernels (gfx950) for one CholeskyQR pass and the CholeskyQR2 driver:
+//   Gram  W = AᵀA              (paper: Syrk, Section "Preliminaries"; Algorithm 4 step 1)
+//   CholInv(W) -> R, R^{-1}    (Algorithm 2)
+//   Q = A R^{-1}               (Algorithm 4 step 3, MM with an upper-triangular right factor)
+//   R = R2 R1                  (Algorithm 5, last step)
+// All arithmetic is IEEE FP64.  Reductions use fixed orders (no FP atomics),
+// so results are bit-reproducible for a given (m, n, lda, device).
+#include "cqr2_internal.h"
+
+#include <hip/hip_runtime.h>
+#include <cmath>
+#include <cstdint>
+
+namespace cqr2 {
+
+// ============================================================================
+// Gram matrix: split-K over 64-row stages, FP64 MFMA 4x4x4 (4 blocks).
+//
+// v_mfma_f64_4x4x4_4b_f64, per lane l: block = (l>>2)&3; A operand row i = l&3,
+// B operand column j = l&3, both with reduction index k = l>>4; result row
+// i = l>>4, column j = l&3.  If lane l holds A[row0 + (l>>2)][4c + (l&3)] for a
+// 4-column group c (a "fragment"), then mfma(frag(I), frag(J)) adds to block b
+// the partial Gram of columns 4I..4I+3 x 4J..4J+3 over the 4 rows
+// row0 + 4k + b: the four hardware blocks act as a 4-way split of the 16 rows.
+// The four partial sums are added (lanes l, l^4, l^8, l^12) once at the end.
+//
+// Work split inside a workgroup: the block-lower-triangle rows I = 0..NG-1
+// (row I has I+1 blocks) are dealt to waves in snake order, which gives every
+// wave the same number of MFMAs when NG is a multiple of 2*NW.
+// ============================================================================
+constexpr int kGramSplits = 256;  // workgroups along m for large m (one per MI355X CU)
+constexpr int kStageRows = 64;  // rows of A per LDS stage (one 512-byte segment per column)
+
+// LDS layout of a stage: column-major, 64 doubles per column, and the rows of
+// odd columns stored XOR 16 so the four columns of a fragment read fall on
+// disjoint bank halves (two passes per fragment, the minimum for 512 bytes).
+__device__ __forceinline__ int stage_pos(int c, int r) { return c * kStageRows + (r ^ ((c & 1) << 4)); }
+
+template <int NG, int NW>
+struct GramLayout {
+  static constexpr int wave_of_row(int I) {
+    const int P = 2 * NW;
+    const int rr = I % P;
+    return rr < NW ? rr : P - 1 - rr;
+  }
+  static constexpr int blocks_of(int w) {
+    int c = 0;
+    for (int I = 0; I < NG; ++I)
+      if (wave_of_row(I) == w) c += I + 1;
+    return c;
+  }
+  static constexpr int max_row(int w) {
+    int mx = -1;
+    for (int I = 0; I < NG; ++I)
+      if (wave_of_row(I) == w) mx = I;
+    return mx;
+  }
+};
+
+template <int NG, int NW, int W>
+struct WaveBlocks {
+  using L = GramLayout<NG, NW>;
+  static constexpr int count = L::blocks_of(W);
+  static constexpr int cap = count > 0 ? count : 1;
+  struct List {
+    int I[cap];
+    int J[cap];
+  };
+  static constexpr List make() {
+    List l{};
+    int k = 0;
+    for (int I = 0; I < NG; ++I)
+      if (L::wave_of_row(I) == W)
+        for (int J = 0; J <= I; ++J) {
+          l.I[k] = I;
+          l.J[k] = J;
+          ++k;
+        }
+    return l;
+  }
+  static constexpr List list = make();
+};
+
+template <int NG, int NW>
+struct GramStage {
+  static constexpr int kCols = 4 * NG;
+  static constexpr int kThreads = NW * 64;
+  static constexpr int kBuf = kCols * kStageRows;  // doubles per stage buffer
+
+  // Asynchronous global -> LDS copy of a full stage (all 64 rows < m).  One
+  // instruction moves 1 KB = two columns x 64 rows; lane i takes two rows of
+  // column 2p + (i >= 32), pre-swizzled so the LDS image matches stage_pos.
+  // Needs A 16-byte aligned and lda even.  Columns >= n are never loaded.
+  __device__ static inline void load_direct(const double* A, int n, int64_t lda, int64_t row0, double* buf,
+                                            int wave, int lane) {
+    const int hi = lane >> 5;
+    const int lrow = 2 * (lane & 31);
+    const int grow = lrow ^ (hi << 4);
+    for (int p = wave; p < kCols / 2; p += NW) {
+      const int col = 2 * p + hi;
+      if (col < n) {
+        const double* src = A + row0 + grow + (int64_t)col * lda;
+        __builtin_amdgcn_global_load_lds((const void*)src,
+                                         (__attribute__((address_space(3))) void*)(buf + 2 * p * kStageRows),
+                                         16, 0, 0);
+      }
+    }
+  }
+  // Register path (ragged last stage, or unaligned A): masked loads, zero fill.
+  __device__ static inline void load_regs(const double* A, int64_t m, int n, int64_t lda, int64_t row0, double* buf,
+                                          int tid) {
+    for (int e = tid; e < kCols * kStageRows; e += kThreads) {
+      const int c = e / kStageRows, r = e % kStageRows;
+      const int64_t row = row0 + r;
+      buf[stage_pos(c, r)] = (row < m && c < n) ? A[row + (int64_t)c * lda] : 0.0;
+    }
+  }
+};
+
+template <int NG, int NW, int W>
+__device__ __forceinline__ void gram_wave_body(const double* __restrict__ A, int64_t m, int n, int64_t lda,
+                                               int64_t st0, int64_t st1, bool direct_ok, double* lds,
+                                               double* __restrict__ out) {
+  using WB = WaveBlocks<NG, NW, W>;
+  using ST = GramStage<NG, NW>;
+  constexpr int MR = GramLayout<NG, NW>::max_row(W);
+  constexpr int NF = MR >= 0 ? MR + 1 : 1;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+
+  double acc[WB::cap];
+#pragma unroll
+  for (int b = 0; b < WB::cap; ++b) acc[b] = 0.0;
+
+  // Columns >= n are never loaded by the direct path: zero them once.
+  for (int e = tid; e < 2 * ST::kBuf; e += ST::kThreads) {
+    const int c = (e % ST::kBuf) / kStageRows;
+    if (c >= n) lds[e] = 0.0;
+  }
+  auto fill = [&](int64_t st, double* buf) {
+    const int64_t row0 = st * kStageRows;
+    if (direct_ok && row0 + kStageRows <= m)
+      ST::load_direct(A, n, lda, row0, buf, W, lane);
+    else
+      ST::load_regs(A, m, n, lda, row0, buf, tid);
+  };
+  if (st0 < st1) fill(st0, lds);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+
+  // Fragment c of k-step t: lane l reads row 16t + (l>>2) of column 4c + (l&3).
+  const int fcol = lane & 3;
+  const int frow = lane >> 2;
+  for (int64_t st = st0; st < st1; ++st) {
+    const int cur = (int)((st - st0) & 1);
+    double* bcur = lds + cur * ST::kBuf;
+    double* bnext = lds + (cur ^ 1) * ST::kBuf;
+    if (st + 1 < st1) fill(st + 1, bnext);
+    if constexpr (WB::count > 0) {
+#pragma unroll 1
+      for (int t = 0; t < kStageRows / 16; ++t) {
+        const int r = 16 * t + frow;
+        double f[NF];
+#pragma unroll
+        for (int c = 0; c < NF; ++c) f[c] = bcur[stage_pos(4 * c + fcol, r)];
+#pragma unroll
+        for (int b = 0; b < WB::count; ++b)
+          acc[b] = __builtin_amdgcn_mfma_f64_4x4x4f64(f[WB::list.I[b]], f[WB::list.J[b]], acc[b], 0, 0, 0);
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+  }
+  // Add the four k-split partial sums held by lanes l, l^4, l^8, l^12.
+  if constexpr (WB::count > 0) {
+#pragma unroll
+    for (int b = 0; b < WB::count; ++b) {
+      double v = acc[b];
+      v += __shfl_xor(v, 4);
+      v += __shfl_xor(v, 8);
+      if (((lane >> 2) & 3) == 0) {
+        const int I = WB::list.I[b], J = WB::list.J[b];
+        const int bidx = I * (I + 1) / 2 + J;
+        out[bidx * 16 + (lane >> 4) * 4 + (lane & 3)] = v;
+      }
+    }
+  }
+}
+
+template <int NG, int NW>
+__global__ __launch_bounds__(NW * 64) void k_gram_partials(const double* __restrict__ A, int64_t m, int n,
+                                                           int64_t lda, int64_t stages, int64_t spw,
+                                                           double* __restrict__ partials,
+                                                           const int32_t* __restrict__ info) {
+  __shared__ double lds[2 * GramStage<NG, NW>::kBuf];
+  if (info != nullptr && *info != 0) return;
+  constexpr int nblk = NG * (NG + 1) / 2;
+  const int64_t st0 = (int64_t)blockIdx.x * spw;
+  const int64_t st1 = st0 + spw < stages ? st0 + spw : stages;
+  const bool direct_ok = (((uintptr_t)A & 15u) == 0) && ((lda & 1) == 0);
+  double* out = partials + (int64_t)blockIdx.x * nblk * 16;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  switch (wave) {
+    case 0: gram_wave_body<NG, NW, 0>(A, m, n, lda, st0, st1, direct_ok, lds, out); break;
+    case 1: if constexpr (NW > 1) gram_wave_body<NG, NW, 1>(A, m, n, lda, st0, st1, direct_ok, lds, out); break;
+    case 2: if constexpr (NW > 2) gram_wave_body<NG, NW, 2>(A, m, n, lda, st0, st1, direct_ok, lds, out); break;
+    case 3: if constexpr (NW > 3) gram_wave_body<NG, NW, 3>(A, m, n, lda, st0, st1, direct_ok, lds, out); break;
+    case 4: if constexpr (NW > 4) gram_wave_body<NG, NW, 4>(A, m, n, lda, st0, st1, direct_ok, lds, out); break;
+    case 5: if constexpr (NW > 5) gram_wave_body<NG, NW, 5>(A, m, n, lda, st0, st1, direct_ok, lds, out); break;
+    case 6: if constexpr (NW > 6) gram_wave_body<NG, NW, 6>(A, m, n, lda, st0, st1, direct_ok, lds, out); break;
+    case 7: if constexpr (NW > 7) gram_wave_body<NG, NW, 7>(A, m, n, lda, st0, st1, direct_ok, lds, out); break;
+    default: break;
+  }
+}
+
+// Fixed-order sum of the per-workgroup partial Grams: 8 threads per entry each
+// add a contiguous range of partials in order, then the 8 results are added in
+// order.  Writes the lower triangle and its mirror.
+__global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ part, int splits, int nblk, int n,
+                                                     double* __restrict__ W, int64_t ldw,
+                                                     const int32_t* __restrict__ info) {
+  __shared__ double red[8][32];
+  if (info != nullptr && *info != 0) return;
+  const int lane = threadIdx.x & 31;
+  const int sub = threadIdx.x >> 5;
+  const int total = nblk * 16;
+  const int e = blockIdx.x * 32 + lane;
+  double v = 0.0;
+  if (e < total) {
+    const int s0 = (splits * sub) / 8, s1 = (splits * (sub + 1)) / 8;
+    for (int s = s0; s < s1; ++s) v += part[(int64_t)s * total + e];
+  }
+  red[sub][lane] = v;
+  __syncthreads();
+  if (sub == 0 && e < total) {
+    double t = red[0][lane];
+#pragma unroll
+    for (int k = 1; k < 8; ++k) t += red[k][lane];
+    const int b = e >> 4, ij = e & 15;
+    int I = (int)((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
+    while (I * (I + 1) / 2 > b) --I;
+    while ((I + 1) * (I + 2) / 2 <= b) ++I;
+    const int J = b - I * (I + 1) / 2;
+    const int row = 4 * I + (ij >> 2), col = 4 * J + (ij & 3);
+    if (row >= col && row < n) {
+      W[row + (int64_t)col * ldw] = t;
+      W[col + (int64_t)row * ldw] = t;
+    }
+  }
+}
+
+static int pow2_at_least(int x) {
+  int p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+// The split count depends only on (m, n) -- never on the device -- so the
+// summation order, and with it every result bit, is the same on any GPU.
+GramPlan plan_gram(int64_t m, int64_t n) {
+  GramPlan p{};
+  const int groups = (int)((n + 3) / 4);
+  p.ng = pow2_at_least(groups < 1 ? 1 : groups);
+  p.nw = p.ng >= 16 ? 8 : (p.ng >= 2 ? p.ng / 2 : 1);
+  p.nblk = p.ng * (p.ng + 1) / 2;
+  p.stages = (m + kStageRows - 1) / kStageRows;
+  if (p.stages < 1) p.stages = 1;
+  const int64_t target = kGramSplits;
+  // Small problems: do not spread fewer than 4 stages per workgroup.
+  int64_t s = p.stages / 4;
+  if (s < 1) s = 1;
+  if (s > target) s = target;
+  p.stages_per_wg = (p.stages + s - 1) / s;
+  p.splits = (int)((p.stages + p.stages_per_wg - 1) / p.stages_per_wg);
+  p.partial_bytes = (size_t)p.splits * p.nblk * 16 * sizeof(double);
+  return p;
+}
+
+hipError_t launch_gram_partials(const GramPlan& p, const double* A, int64_t m, int n, int64_t lda,
+                                double* partials, const int32_t* info, hipStream_t s) {
+  dim3 grid(p.splits);
+#define CQR2_GRAM_CASE(NGV, NWV)                                                                     \
+  case NGV:                                                                                          \
+    hipLaunchKernelGGL((k_gram_partials<NGV, NWV>), grid, dim3(NWV * 64), 0, s, A, m, n, lda,        \
+                       p.stages, p.stages_per_wg, partials, info);                                   \
+    break;
+  switch (p.ng) {
+    CQR2_GRAM_CASE(1, 1)
+    CQR2_GRAM_CASE(2, 1)
+    CQR2_GRAM_CASE(4, 2)
+    CQR2_GRAM_CASE(8, 4)
+    CQR2_GRAM_CASE(16, 8)
+    CQR2_GRAM_CASE(32, 8)
+    default: return hipErrorInvalidValue;
+  }
+#undef CQR2_GRAM_CASE
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_reduce(const GramPlan& p, const double* partials, int n, double* W, int64_t ldw,
+                              const int32_t* info, hipStream_t s) {
+  const int total = p.nblk * 16;
+  dim3 grid((total + 31) / 32);
+  hipLaunchKernelGGL(k_gram_reduce, grid, dim3(256), 0, s, partials, p.splits, p.nblk, n, W, ldw, info);
+  return hipGetLastError();
+}
+
+// ============================================================================
+// CholInv (Algorithm 2) for n <= 128 in one workgroup.
+//
+// The recursion's net effect, column by column: pivot d = W'(j,j), L(j,j) =
+// sqrt(d), Y(j,j) = 1/L(j,j); L(i,j) = W'(i,j) * Y(j,j) (Algorithm 2's
+// L21 = A21 Y11ᵀ at its 1x1 base); Schur update W' -= L(:,j) L(:,j)ᵀ; and the
+// inverse's update Z(i,k) -= L(i,j) Y(j,k) (Y21 = -Y22 L21 Y11 unrolled).
+// The n x n register-resident matrix M holds W' / L in its lower triangle and
+// Zᵀ / Yᵀ (= R^{-1}) in its strict upper triangle; thread (r, c) of a 16 x 16
+// grid owns M(r + 16a, c + 16b) (a cyclic distribution, so the shrinking
+// trailing matrix stays spread over all threads).  One barrier per column:
+// the owners of column j publish it to a double-buffered LDS vector, every
+// thread forms L(:,j) and Y(j,:) from it and applies the rank-1 updates.
+// ============================================================================
+template <int T>
+__global__ __launch_bounds__(256) void k_cholinv(const double* __restrict__ W, int64_t ldw, int n,
+                                                 double* __restrict__ R, int64_t ldr, double* __restrict__ Rinv,
+                                                 int64_t ldri, double* __restrict__ Upad, int np,
+                                                 int32_t* __restrict__ info, int info_offset) {
+  constexpr int NP = 16 * T;
+  __shared__ double colbuf[2][NP];
+  const int tid = threadIdx.x;
+  const int r = tid >> 4, c = tid & 15;
+  int fail = 0;
+  if (info != nullptr && *info != 0) fail = -1;  // an earlier phase failed: skip, NaN outputs
+
+  double M[T][T];
+#pragma unroll
+  for (int a = 0; a < T; ++a)
+#pragma unroll
+    for (int b = 0; b < T; ++b) {
+      const int p = r + 16 * a, q = c + 16 * b;
+      double v = 0.0;
+      if (p >= q) v = (p < n) ? W[p + (int64_t)q * ldw] : (p == q ? 1.0 : 0.0);
+      M[a][b] = v;
+    }
+
+  if (fail == 0) {
+#pragma unroll
+    for (int jb = 0; jb < T; ++jb) {
+      if (16 * jb >= n || fail != 0) break;
+      for (int jc = 0; jc < 16; ++jc) {
+        const int j = 16 * jb + jc;
+        if (j >= n) break;
+        double* buf = colbuf[j & 1];
+        if (c == jc) {
+#pragma unroll
+          for (int a = 0; a < T; ++a) buf[r * T + a] = M[a][jb];
+        }
+        __syncthreads();
+        const double d = buf[jc * T + jb];
+        if (!(d > 0.0)) {  // non-positive or NaN pivot (uniform across the workgroup)
+          fail = j + 1;
+          break;
+        }
+        const double sd = sqrt(d);
+        const double y = 1.0 / sd;
+        double lvp[T], yvp[T], lvq[T];
+#pragma unroll
+        for (int a = 0; a < T; ++a) {
+          const int p = r + 16 * a;
+          const double v = buf[r * T + a];
+          lvp[a] = (p > j) ? v * y : 0.0;
+          yvp[a] = (p < j) ? v * y : (p == j ? y : 0.0);
+        }
+#pragma unroll
+        for (int b = 0; b < T; ++b) {
+          const int q = c + 16 * b;
+          lvq[b] = (q > j) ? buf[c * T + b] * y : 0.0;
+        }
+        if (c == jc) {
+#pragma unroll
+          for (int a = 0; a < T; ++a) {
+            const int p = r + 16 * a;
+            M[a][jb] = (p > j) ? lvp[a] : (p == j ? sd : yvp[a]);
+          }
+        }
+        const bool low_diag = r >= c;  // element (a,a) of this thread is in the lower triangle
+#pragma unroll
+        for (int b = jb; b < T; ++b) {
+#pragma unroll
+          for (int a = 0; a < T; ++a) {
+            if (a > b) {
+              M[a][b] = fma(-lvp[a], lvq[b], M[a][b]);
+            } else if (a < b) {
+              if (a <= jb) M[a][b] = fma(-yvp[a], lvq[b], M[a][b]);
+            } else {
+              const double f = low_diag ? lvp[a] : yvp[a];
+              M[a][b] = fma(-f, lvq[b], M[a][b]);
+            }
+          }
+        }
+      }
+    }
+  }
+
+  const double nan = __builtin_nan("");
+  if (fail > 0 && tid == 0 && info != nullptr) *info = info_offset + fail;
+#pragma unroll
+  for (int a = 0; a < T; ++a)
+#pragma unroll
+    for (int b = 0; b < T; ++b) {
+      const int p = r + 16 * a, q = c + 16 * b;
+      const double v = M[a][b];
+      if (p < n && q < n) {
+        if (p >= q) {
+          R[q + (int64_t)p * ldr] = fail ? nan : v;  // R(q,p) = L(p,q)
+          if (p > q) R[p + (int64_t)q * ldr] = 0.0;
+        }
+        if (Rinv != nullptr) {
+          if (p < q) {
+            Rinv[p + (int64_t)q * ldri] = fail ? nan : v;
+            Rinv[q + (int64_t)p * ldri] = 0.0;
+          } else if (p == q) {
+            Rinv[p + (int64_t)p * ldri] = fail ? nan : 1.0 / v;
+          }
+        }
+      }
+      if (Upad != nullptr && p < np && q < np) {
+        double u = 0.0;
+        if (p < q) u = v;
+        else if (p == q) u = 1.0 / v;
+        Upad[(int64_t)p * np + q] = fail ? nan : u;
+      }
+    }
+}
+
+int padded_order(int64_t n) {
+  if (n <= 32) return 32;
+  if (n <= 64) return 64;
+  return 128;
+}
+
+hipError_t launch_cholinv(const double* W, int64_t ldw, int n, double* R, int64_t ldr, double* Rinv,
+                          int64_t ldri, double* Upad, int np, int32_t* info, int info_offset,
+                          hipStream_t s) {
+  const int t = padded_order(n) / 16;
+  switch (t) {
+    case 2: hipLaunchKernelGGL(k_cholinv<2>, dim3(1), dim3(256), 0, s, W, ldw, n, R, ldr, Rinv, ldri, Upad, np, info, info_offset); break;
+    case 4: hipLaunchKernelGGL(k_cholinv<4>, dim3(1), dim3(256), 0, s, W, ldw, n, R, ldr, Rinv, ldri, Upad, np, info, info_offset); break;
+    case 8: hipLaunchKernelGGL(k_cholinv<8>, dim3(1), dim3(256), 0, s, W, ldw, n, R, ldr, Rinv, ldri, Upad, np, info, info_offset); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ============================================================================
+// Q = A U with U upper triangular (NT x NT padded, NT = 32, 64 or 128), FP64
+// MFMA 4x4x4 (4 blocks).
+//
+// The four hardware blocks are four groups of 4 rows of A that share one 4x4
+// fragment of U: with lane l holding A(row0 + (l&15), 4I + (l>>4)) and
+// U(4I + (l>>4), 4J + (l&3)), mfma adds to output lane l the product for
+// row row0 + 4((l>>2)&3) + (l>>4), column 4J + (l&3).  A is read straight from
+// global memory (per instruction: 4 columns x 128 contiguous bytes); U is
+// staged once per workgroup into LDS as the packed upper-triangle fragments
+// (J >= I only, so the triangle costs nothing).  Each wave owns whole rows of
+// Q, so Q == A (in place) needs no synchronization, and every wave does the
+// same work regardless of the triangle.
+// ============================================================================
+template <int NG>
+struct UFrags {
+  static constexpr int count = NG * (NG + 1) / 2;
+  // row I of the packed triangle starts after sum_{r<I} (NG - r) fragments
+  static constexpr int index(int I, int J) { return I * NG - I * (I - 1) / 2 + (J - I); }
+};
+
+template <int NT, int RT>
+__global__ __launch_bounds__(256) void k_apply_rinv(const double* A, int64_t m, int n, int64_t lda,
+                                                    const double* __restrict__ U, int64_t urs, int64_t ucs,
+                                                    double* Q, int64_t ldq, const int32_t* __restrict__ info) {
+  constexpr int NG = NT / 4;
+  constexpr int NF = UFrags<NG>::count;
+  constexpr int ROWS = 16 * RT;  // rows per wave
+  __shared__ double uf[NF * 16];
+  if (info != nullptr && *info != 0) return;
+
+  // Stage the fragments: entry (kk, jj) of fragment (I, J) is U(4I+kk, 4J+jj);
+  // entries below the diagonal or outside n x n are zero.
+  for (int e = threadIdx.x; e < NF * 16; e += blockDim.x) {
+    const int f = e >> 4, w = e & 15;
+    int I = 0;
+    while (UFrags<NG>::index(I + 1, I + 1) <= f && I + 1 < NG) ++I;
+    const int J = I + (f - UFrags<NG>::index(I, I));
+    const int i = 4 * I + (w >> 2), j = 4 * J + (w & 3);
+    double v = 0.0;
+    if (i <= j && j < n) v = U[(int64_t)i * urs + (int64_t)j * ucs];
+    uf[e] = v;
+  }
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int arow = lane & 15;              // A operand: row within a 16-row tile
+  const int acol = lane >> 4;              // A operand: column within a 4-column group
+  const int ubase = (lane >> 4) * 4 + (lane & 3);
+  const int orow = 4 * ((lane >> 2) & 3) + (lane >> 4);  // output row within the tile
+  const int ocol = lane & 3;
+  const int waves = blockDim.x >> 6;
+
+  for (int64_t wb = (int64_t)blockIdx.x * waves + wave; wb * ROWS < m; wb += (int64_t)gridDim.x * waves) {
+    const int64_t row0 = wb * ROWS;
+    const double* ap[RT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      int64_t r = row0 + 16 * rt + arow;
+      if (r > m - 1) r = m - 1;  // rows past m read a valid row; their results are not stored
+      ap[rt] = A + r;
+    }
+    double acc[RT][NG];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int J = 0; J < NG; ++J) acc[rt][J] = 0.0;
+
+    // Entries of A for column group I + PF are requested while group I is
+    // multiplied; the scheduling barrier keeps the compiler from hoisting the
+    // whole unrolled sequence of loads.
+    constexpr int PF = 4;
+    double abuf[PF + 1][RT];
+    auto load_group = [&](int I, double (&dst)[RT]) {
+      int col = 4 * I + acol;
+      if (col > n - 1) col = n - 1;  // columns past n read column n-1; U's rows past n are zero
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) dst[rt] = ap[rt][(int64_t)col * lda];
+    };
+#pragma unroll
+    for (int I = 0; I < PF && I < NG; ++I) load_group(I, abuf[I]);
+#pragma unroll
+    for (int I = 0; I < NG; ++I) {
+      if (I + PF < NG) load_group(I + PF, abuf[(I + PF) % (PF + 1)]);
+      const double(&a)[RT] = abuf[I % (PF + 1)];
+#pragma unroll
+      for (int J = I; J < NG; ++J) {
+        const double u = uf[UFrags<NG>::index(I, J) * 16 + ubase];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) acc[rt][J] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[rt], u, acc[rt][J], 0, 0, 0);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      const int64_t r = row0 + 16 * rt + orow;
+      if (r < m) {
+#pragma unroll
+        for (int J = 0; J < NG; ++J) {
+          const int col = 4 * J + ocol;
+          if (col < n) Q[r + (int64_t)col * ldq] = acc[rt][J];
+        }
+      }
+    }
+  }
+}
+
+hipError_t launch_apply_rinv(const double* A, int64_t m, int n, int64_t lda, const double* U, int64_t urs,
+                             int64_t ucs, double* Q, int64_t ldq, const int32_t* info, int num_cus, hipStream_t s) {
+  const int nt = padded_order(n);
+  constexpr int RT = 2;
+  const int64_t rows_per_wg = 4 * 16 * RT;
+  int64_t wgs = (m + rows_per_wg - 1) / rows_per_wg;
+  const int64_t cap = (int64_t)(num_cus > 0 ? num_cus : 256) * 2;
+  if (wgs > cap) wgs = cap;
+  if (wgs < 1) wgs = 1;
+  dim3 grid((unsigned)wgs), block(256);
+  switch (nt) {
+    case 32: hipLaunchKernelGGL((k_apply_rinv<32, RT>), grid, block, 0, s, A, m, n, lda, U, urs, ucs, Q, ldq, info); break;
+    case 64: hipLaunchKernelGGL((k_apply_rinv<64, RT>), grid, block, 0, s, A, m, n, lda, U, urs, ucs, Q, ldq, info); break;
+    case 128: hipLaunchKernelGGL((k_apply_rinv<128, RT>), grid, block, 0, s, A, m, n, lda, U, urs, ucs, Q, ldq, info); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ============================================================================
+// R = R2 R1 for upper-triangular factors; one thread per entry, ascending k.
+// Also publishes the device info word and NaN-fills R after a breakdown.
+// ============================================================================
+__global__ __launch_bounds__(256) void k_upper_product(const double* __restrict__ R2, const double* __restrict__ R1,
+                                                       int64_t ldin, double* __restrict__ R, int64_t ldr, int n,
+                                                       const int32_t* __restrict__ info,
+                                                       int32_t* __restrict__ user_info) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t st = info != nullptr ? *info : 0;
+  if (e == 0 && user_info != nullptr) *user_info = st;
+  if (e >= (int64_t)n * n) return;
+  const int i = (int)(e % n), j = (int)(e / n);
+  double v = 0.0;
+  if (st != 0) {
+    v = __builtin_nan("");
+  } else if (i <= j) {
+    for (int k = i; k <= j; ++k) v = fma(R2[i + (int64_t)k * ldin], R1[k + (int64_t)j * ldin], v);
+  }
+  R[i + (int64_t)j * ldr] = v;
+}
+
+hipError_t launch_upper_product(const double* R2, const double* R1, int64_t ldin, double* R, int64_t ldr,
+                                int n, const int32_t* info, int32_t* user_info, hipStream_t s) {
+  const int64_t total = (int64_t)n * n;
+  dim3 grid((unsigned)((total + 255) / 256 > 0 ? (total + 255) / 256 : 1));
+  hipLaunchKernelGGL(k_upper_product, grid, dim3(256), 0, s, R2, R1, ldin, R, ldr, n, info, user_info);
+  return hipGetLastError();
+}
+
+__global__ void k_set_info(int32_t* info, int32_t value) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *info = value;
+}
+
+hipError_t launch_set_info(int32_t* info, int32_t value, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_info, dim3(1), dim3(64), 0, s, info, value);
+  return hipGetLastError();
+}
+
+}  // namespace cqr2

@@ -1,0 +1,126 @@
+"""C ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, and rejects invalid arguments before any HIP call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1710_08471_amd as cq
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cqr2.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(cq.LIB_PATH),
+                                reason="libcqr2.so not built (run python -m paper_1710_08471_amd.build)")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cqr2_\w+)\s*\(", text)))
+
+
+def test_header_declares_expected_entry_points():
+    names = declared_functions()
+    for must in ("cqr2_factor", "cqr2_factor_ex", "cqr2_workspace_size", "cqr2_gram", "cqr2_cholinv",
+                 "cqr2_apply_rinv", "cqr2_upper_product", "cqr2_status_string"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(cq.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(declared_functions()) == set(cq.SIGNATURES), "binding signatures out of sync with header"
+
+
+def test_version_and_status_strings():
+    lib = cq.load()
+    assert b"gfx950" in lib.cqr2_version()
+    assert lib.cqr2_status_string(0) == b"success"
+    assert b"HIP" in lib.cqr2_status_string(cq.CQR2_ERR_HIP)
+
+
+FAKE = ctypes.c_void_p(0x10000)        # never dereferenced: validation fails first
+FAKE2 = ctypes.c_void_p(0x10000000)
+NULL = ctypes.c_void_p(0)
+
+
+def test_factor_argument_errors():
+    lib = cq.load()
+    f = lib.cqr2_factor
+    assert f(FAKE, 10, -1, 10, FAKE2, FAKE2, NULL) == -3            # n < 0
+    assert f(FAKE, 3, 5, 5, FAKE2, FAKE2, NULL) == -2               # m < n
+    assert f(FAKE, 10, 5, 9, FAKE2, FAKE2, NULL) == -4              # lda < m
+    assert f(NULL, 10, 5, 10, FAKE2, FAKE2, NULL) == -1             # A NULL
+    assert f(FAKE, 10, 5, 10, NULL, FAKE2, NULL) == -5              # Q NULL
+    assert f(FAKE, 10, 5, 10, FAKE2, NULL, NULL) == -6              # R NULL
+    assert f(ctypes.c_void_p(0x10004), 10, 5, 10, FAKE2, FAKE2, NULL) == -1   # misaligned
+    assert f(FAKE, 10, 5, 10, ctypes.c_void_p(0x10000 + 80), FAKE2, NULL) == -5  # Q overlaps A
+    assert f(FAKE, 1000, 200, 1000, FAKE2, ctypes.c_void_p(0x20000000), NULL) == cq.CQR2_ERR_UNSUPPORTED
+    assert f(NULL, 10, 0, 10, NULL, NULL, NULL) == 0                # n == 0: quick return
+
+
+def test_factor_ex_argument_errors():
+    lib = cq.load()
+    f = lib.cqr2_factor_ex
+    W = ctypes.c_void_p(0x40000000)
+    ws = lib.cqr2_workspace_size(100, 10, 0)
+    assert ws > 0
+    ok = dict(A=FAKE, m=100, n=10, lda=100, Q=FAKE2, ldq=100, R=ctypes.c_void_p(0x30000000), ldr=10,
+              work=W, wb=ws, info=NULL, flags=0)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return f(a["A"], a["m"], a["n"], a["lda"], a["Q"], a["ldq"], a["R"], a["ldr"], a["work"], a["wb"],
+                 a["info"], a["flags"], NULL)
+
+    assert call(ldq=99) == -6
+    assert call(ldr=9) == -8
+    assert call(flags=7) == -12
+    assert call(work=NULL) == -9
+    assert call(work=ctypes.c_void_p(0x40000008)) == -9           # not 256-byte aligned
+    assert call(wb=ws - 1) == -10
+    assert call(info=ctypes.c_void_p(0x50000002)) == -11
+    assert call(R=ctypes.c_void_p(0x10000 + 8)) == -7               # R overlaps A
+    assert call(work=ctypes.c_void_p(0x10000000)) == -9             # workspace overlaps Q
+
+
+def test_workspace_size_contract():
+    lib = cq.load()
+    assert lib.cqr2_workspace_size(10, 20, 0) == 0       # m < n
+    assert lib.cqr2_workspace_size(100, 0, 0) == 0
+    assert lib.cqr2_workspace_size(100, 129, 0) == 0     # beyond the tall-skinny limit
+    small = lib.cqr2_workspace_size(4096, 64, 0)
+    big = lib.cqr2_workspace_size(1 << 20, 128, 0)
+    assert 0 < small < big
+    assert small % 256 == 0 and big % 256 == 0
+    # depends only on the problem, never on the device
+    assert lib.cqr2_workspace_size(1 << 20, 128, 0) == big
+
+
+def test_step_entry_argument_errors():
+    lib = cq.load()
+    assert lib.cqr2_gram(FAKE, 10, 5, 9, FAKE2, 5, FAKE2, 1 << 20, NULL) == -4
+    assert lib.cqr2_gram(FAKE, 10, 5, 10, FAKE2, 4, FAKE2, 1 << 20, NULL) == -6
+    assert lib.cqr2_gram(FAKE, 10, 5, 10, FAKE2, 5, NULL, 1 << 20, NULL) == -7
+    assert lib.cqr2_gram(FAKE, 10, 5, 10, FAKE2, 5, ctypes.c_void_p(0x60000000), 8, NULL) == -8
+    assert lib.cqr2_cholinv(FAKE, 5, 4, FAKE2, ctypes.c_void_p(0x60000000), 5, NULL, NULL) == -3
+    assert lib.cqr2_cholinv(FAKE, 5, 5, FAKE2, FAKE2, 5, NULL, NULL) == -5     # R == Rinv
+    assert lib.cqr2_apply_rinv(FAKE, 10, 5, 10, FAKE2, 4, ctypes.c_void_p(0x60000000), 10, NULL) == -6
+    assert lib.cqr2_apply_rinv(FAKE, 10, 5, 10, FAKE2, 5, FAKE, 11, NULL) == -8  # in place needs ldq == lda
+    assert lib.cqr2_upper_product(FAKE, FAKE2, FAKE, 5, 5, NULL) == -3          # R overlaps R2
+    assert lib.cqr2_upper_product(FAKE, FAKE2, ctypes.c_void_p(0x60000000), 5, 4, NULL) == -5
+
+
+def test_binding_fails_loudly_without_library(tmp_path):
+    import importlib
+    mod = importlib.import_module("paper_1710_08471_amd")
+    saved = mod._lib
+    mod._lib = None
+    try:
+        with pytest.raises(RuntimeError):
+            mod.load(str(tmp_path / "missing.so"))
+    finally:
+        mod._lib = saved
