@@ -51,8 +51,11 @@ extern "C" {
  * recovered by pass 2, the residual is at the FP32 rounding level. */
 #define CQR2_MIXED_P1_FP32 1u
 
-/* Largest n the tall-skinny path handles. */
-#define CQR2_MAX_N 128
+/* Largest n accepted (every n x n workspace block is n*n*8 bytes).  Up to
+ * n = 128 the tall-skinny kernels run (split-K Gram, one-workgroup CholInv,
+ * streaming Q = A R^{-1}); above, the Gram, Q formation and R2 R1 are tiled
+ * GEMMs and CholInv is the recursion of Algorithm 2 with a 128 base case. */
+#define CQR2_MAX_N 16384
 
 /*
  * cqr2_factor — CholeskyQR2 of A (Algorithm 5), FP64.

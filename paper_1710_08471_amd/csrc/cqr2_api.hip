@@ -17,6 +17,7 @@ namespace {
 using cqr2::GramPlan;
 
 constexpr size_t kAlign = 256;
+constexpr int64_t kSmallN = 128;  // tall-skinny kernels: Gram, CholInv and Q = A R^-1 up to this n
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -44,16 +45,16 @@ int device_cus() {
   return cus;
 }
 
-// Workspace layout of one factorization.
-struct Layout {
+// Workspace layout of one factorization with n <= 128.
+struct SmallLayout {
   GramPlan gram;
   int np = 0;
   size_t off_info = 0, off_part = 0, off_w = 0, off_u1 = 0, off_u2 = 0, off_r1 = 0, off_r2 = 0;
   size_t total = 0;
 };
 
-Layout make_layout(int64_t m, int64_t n) {
-  Layout L;
+SmallLayout make_small_layout(int64_t m, int64_t n) {
+  SmallLayout L;
   L.gram = cqr2::plan_gram(m, n);
   L.np = cqr2::padded_order(n);
   size_t off = 0;
@@ -68,6 +69,10 @@ Layout make_layout(int64_t m, int64_t n) {
   return L;
 }
 
+size_t factor_workspace(int64_t m, int64_t n) {
+  return n <= kSmallN ? make_small_layout(m, n).total : cqr2::plan_general(m, n).total;
+}
+
 // ---- timing instrumentation -------------------------------------------------
 struct Timer {
   bool enabled = false;
@@ -75,6 +80,7 @@ struct Timer {
   size_t used = 0;
   struct Rec { int cls; hipEvent_t a, b; };
   std::vector<Rec> recs;
+  hipEvent_t open[CQR2_NUM_TIMERS] = {};
 };
 Timer g_timer;
 std::mutex g_timer_mu;
@@ -88,27 +94,34 @@ hipEvent_t timer_event() {
   return g_timer.pool[g_timer.used++];
 }
 
-struct Scope {
-  int cls;
-  hipStream_t s;
-  hipEvent_t a = nullptr;
-  Scope(int c, hipStream_t st) : cls(c), s(st) {
-    if (!g_timer.enabled) return;
-    std::lock_guard<std::mutex> g(g_timer_mu);
-    a = timer_event();
-    if (a) hipEventRecord(a, s);
-  }
-  ~Scope() {
-    if (!g_timer.enabled || a == nullptr) return;
-    std::lock_guard<std::mutex> g(g_timer_mu);
-    hipEvent_t b = timer_event();
-    if (b == nullptr) return;
-    hipEventRecord(b, s);
-    g_timer.recs.push_back({cls, a, b});
-  }
-};
+void timer_begin(int cls, hipStream_t s) {
+  if (!g_timer.enabled || cls < 0 || cls >= CQR2_NUM_TIMERS) return;
+  std::lock_guard<std::mutex> g(g_timer_mu);
+  hipEvent_t a = timer_event();
+  if (a && hipEventRecord(a, s) == hipSuccess) g_timer.open[cls] = a;
+}
 
-// ---- library-cached workspace for the 7-argument form -----------------------
+void timer_end(int cls, hipStream_t s) {
+  if (!g_timer.enabled || cls < 0 || cls >= CQR2_NUM_TIMERS) return;
+  std::lock_guard<std::mutex> g(g_timer_mu);
+  hipEvent_t a = g_timer.open[cls];
+  if (a == nullptr) return;
+  g_timer.open[cls] = nullptr;
+  hipEvent_t b = timer_event();
+  if (b == nullptr || hipEventRecord(b, s) != hipSuccess) return;
+  g_timer.recs.push_back({cls, a, b});
+}
+
+cqr2::TimerHook timer_hook() {
+  cqr2::TimerHook h;
+  if (g_timer.enabled) {
+    h.b = timer_begin;
+    h.e = timer_end;
+  }
+  return h;
+}
+
+// ---- library-cached workspace for the entry points without a work argument --
 struct CachedWs {
   void* ptr = nullptr;
   size_t bytes = 0;
@@ -122,11 +135,12 @@ void* cached_workspace(size_t bytes, int* err) {
   if (hipGetDevice(&dev) != hipSuccess) { *err = CQR2_ERR_HIP; return nullptr; }
   if ((int)g_ws.size() <= dev) g_ws.resize(dev + 1);
   CachedWs& w = g_ws[dev];
+  if (bytes == 0) bytes = kAlign;
   if (w.bytes < bytes) {
     if (w.ptr) {
       // The previous workspace may still be used by enqueued work.
       if (hipDeviceSynchronize() != hipSuccess) { *err = CQR2_ERR_HIP; return nullptr; }
-      hipFree(w.ptr);
+      (void)hipFree(w.ptr);
       w.ptr = nullptr;
       w.bytes = 0;
     }
@@ -147,9 +161,10 @@ int check_hip(hipError_t e) { return e == hipSuccess ? 0 : CQR2_ERR_HIP; }
     if (_rc != 0) return _rc;     \
   } while (0)
 
-// The enqueued CholeskyQR2 sequence; arguments already validated.
-int run_factor(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, int64_t ldq, double* R,
-               int64_t ldr, char* ws, const Layout& L, int32_t* d_info, hipStream_t s, int cus) {
+// The enqueued CholeskyQR2 sequence for n <= 128; arguments already validated.
+int run_small(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, int64_t ldq, double* R, int64_t ldr,
+              char* ws, const SmallLayout& L, int32_t* d_info, hipStream_t s, int cus) {
+  const cqr2::TimerHook th = timer_hook();
   int32_t* info = (int32_t*)(ws + L.off_info);
   double* part = (double*)(ws + L.off_part);
   double* W = (double*)(ws + L.off_w);
@@ -160,25 +175,37 @@ int run_factor(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, in
   const int ni = (int)n;
   CQR2_TRY(cqr2::launch_set_info(info, 0, s));
   // ---- pass 1: CQR(A) ----
-  { Scope t(0, s); CQR2_TRY(cqr2::launch_gram_partials(L.gram, A, m, ni, lda, part, info, s)); }
-  { Scope t(1, s); CQR2_TRY(cqr2::launch_gram_reduce(L.gram, part, ni, W, n, info, s)); }
-  { Scope t(2, s); CQR2_TRY(cqr2::launch_cholinv(W, n, ni, R1, n, nullptr, 0, U1, L.np, info, 0, s)); }
-  { Scope t(3, s); CQR2_TRY(cqr2::launch_apply_rinv(A, m, ni, lda, U1, L.np, 1, Q, ldq, info, cus, s)); }
+  th.begin(0, s); CQR2_TRY(cqr2::launch_gram_partials(L.gram, A, m, ni, lda, part, info, s)); th.end(0, s);
+  th.begin(1, s); CQR2_TRY(cqr2::launch_gram_reduce(L.gram, part, ni, W, n, info, s)); th.end(1, s);
+  th.begin(2, s); CQR2_TRY(cqr2::launch_cholinv(W, n, ni, R1, n, nullptr, 0, U1, L.np, info, 0, s)); th.end(2, s);
+  th.begin(3, s); CQR2_TRY(cqr2::launch_apply_rinv(A, m, ni, lda, U1, L.np, 1, Q, ldq, info, cus, s)); th.end(3, s);
   // ---- pass 2: CQR(Q1), in place ----
-  { Scope t(0, s); CQR2_TRY(cqr2::launch_gram_partials(L.gram, Q, m, ni, ldq, part, info, s)); }
-  { Scope t(1, s); CQR2_TRY(cqr2::launch_gram_reduce(L.gram, part, ni, W, n, info, s)); }
-  { Scope t(2, s); CQR2_TRY(cqr2::launch_cholinv(W, n, ni, R2, n, nullptr, 0, U2, L.np, info, ni, s)); }
-  { Scope t(4, s); CQR2_TRY(cqr2::launch_apply_rinv(Q, m, ni, ldq, U2, L.np, 1, Q, ldq, info, cus, s)); }
-  // ---- R = R2 R1 ----
-  { Scope t(5, s); CQR2_TRY(cqr2::launch_upper_product(R2, R1, n, R, ldr, ni, info, d_info, s)); }
+  th.begin(0, s); CQR2_TRY(cqr2::launch_gram_partials(L.gram, Q, m, ni, ldq, part, info, s)); th.end(0, s);
+  th.begin(1, s); CQR2_TRY(cqr2::launch_gram_reduce(L.gram, part, ni, W, n, info, s)); th.end(1, s);
+  th.begin(2, s); CQR2_TRY(cqr2::launch_cholinv(W, n, ni, R2, n, nullptr, 0, U2, L.np, info, ni, s)); th.end(2, s);
+  th.begin(4, s); CQR2_TRY(cqr2::launch_apply_rinv(Q, m, ni, ldq, U2, L.np, 1, Q, ldq, info, cus, s)); th.end(4, s);
+  // ---- R = R2 R1 (W is free again) ----
+  th.begin(5, s);
+  CQR2_TRY(cqr2::launch_gemm(0, 0, n, n, n, 1.0, R2, n, R1, n, 0.0, W, n,
+                             cqr2::GEMM_A_UPPER | cqr2::GEMM_B_UPPER | cqr2::GEMM_C_UPPER, 1, nullptr, info, s));
+  CQR2_TRY(cqr2::launch_finalize_r(W, n, R, ldr, n, info, d_info, s));
+  th.end(5, s);
   return 0;
+}
+
+int run_factor(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, int64_t ldq, double* R, int64_t ldr,
+               char* ws, int32_t* d_info, hipStream_t s) {
+  if (n <= kSmallN)
+    return run_small(A, m, n, lda, Q, ldq, R, ldr, ws, make_small_layout(m, n), d_info, s, device_cus());
+  const cqr2::GeneralPlan p = cqr2::plan_general(m, n);
+  return check_hip(cqr2::factor_general(A, m, n, lda, Q, ldq, R, ldr, ws, p, d_info, s, timer_hook()));
 }
 
 }  // namespace
 
 extern "C" {
 
-const char* cqr2_version(void) { return "cqr2-mi355x 0.1 (gfx950)"; }
+const char* cqr2_version(void) { return "cqr2-mi355x 0.2 (gfx950)"; }
 
 const char* cqr2_status_string(int code) {
   switch (code) {
@@ -192,8 +219,8 @@ const char* cqr2_status_string(int code) {
 }
 
 size_t cqr2_workspace_size(int64_t m, int64_t n, uint32_t flags) {
-  if (m < n || n < 1 || n > CQR2_MAX_N || flags != CQR2_FP64) return 0;
-  return make_layout(m, n).total;
+  if (m < n || n < 1 || flags != CQR2_FP64 || n > CQR2_MAX_N) return 0;
+  return factor_workspace(m, n);
 }
 
 int cqr2_factor_ex(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, int64_t ldq, double* R,
@@ -211,19 +238,18 @@ int cqr2_factor_ex(const double* A, int64_t m, int64_t n, int64_t lda, double* Q
   if (Q == nullptr || !aligned8(Q)) return -5;
   if (R == nullptr || !aligned8(R)) return -7;
   if (n > CQR2_MAX_N) return CQR2_ERR_UNSUPPORTED;
-  if (lda > (int64_t)1 << 40 || ldq > (int64_t)1 << 40) return lda > ((int64_t)1 << 40) ? -4 : -6;
   const size_t abytes = matrix_bytes(m, n, lda), qbytes = matrix_bytes(m, n, ldq), rbytes = matrix_bytes(n, n, ldr);
   if (overlaps(A, abytes, Q, qbytes)) return -5;
   if (overlaps(A, abytes, R, rbytes)) return -7;
   if (overlaps(Q, qbytes, R, rbytes)) return -7;
-  const Layout L = make_layout(m, n);
+  const size_t need = factor_workspace(m, n);
   if (work == nullptr || ((uintptr_t)work % kAlign) != 0) return -9;
-  if (work_bytes < L.total) return -10;
+  if (work_bytes < need) return -10;
   if (overlaps(work, work_bytes, A, abytes) || overlaps(work, work_bytes, Q, qbytes) ||
       overlaps(work, work_bytes, R, rbytes))
     return -9;
   if (d_info != nullptr && ((uintptr_t)d_info & 3u) != 0) return -11;
-  return run_factor(A, m, n, lda, Q, ldq, R, ldr, (char*)work, L, d_info, (hipStream_t)stream, device_cus());
+  return run_factor(A, m, n, lda, Q, ldq, R, ldr, (char*)work, d_info, (hipStream_t)stream);
 }
 
 int cqr2_factor(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, double* R, void* stream) {
@@ -238,16 +264,17 @@ int cqr2_factor(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, d
   const size_t abytes = matrix_bytes(m, n, lda), rbytes = matrix_bytes(n, n, n);
   if (overlaps(A, abytes, Q, abytes)) return -5;
   if (overlaps(A, abytes, R, rbytes) || overlaps(Q, abytes, R, rbytes)) return -6;
-  const Layout L = make_layout(m, n);
   int err = 0;
-  void* ws = cached_workspace(L.total, &err);
+  void* ws = cached_workspace(factor_workspace(m, n), &err);
   if (err) return err;
-  return run_factor(A, m, n, lda, Q, lda, R, n, (char*)ws, L, nullptr, (hipStream_t)stream, device_cus());
+  return run_factor(A, m, n, lda, Q, lda, R, n, (char*)ws, nullptr, (hipStream_t)stream);
 }
 
 size_t cqr2_gram_workspace_size(int64_t m, int64_t n) {
   if (m < 0 || n < 1 || n > CQR2_MAX_N) return 0;
-  return align_up(cqr2::plan_gram(m, n).partial_bytes);
+  if (n <= kSmallN) return align_up(cqr2::plan_gram(m, n).partial_bytes);
+  const int splits = cqr2::gemm_pick_splits(n, n, m, cqr2::kPlanCUs);
+  return align_up(cqr2::gemm_workspace_bytes(n, n, splits) + 8);
 }
 
 int cqr2_gram(const double* A, int64_t m, int64_t n, int64_t lda, double* W, int64_t ldw, void* work,
@@ -260,16 +287,25 @@ int cqr2_gram(const double* A, int64_t m, int64_t n, int64_t lda, double* W, int
   if ((m > 0 && A == nullptr) || !aligned8(A)) return -1;  // A is not read when m == 0
   if (W == nullptr || !aligned8(W)) return -5;
   if (n > CQR2_MAX_N) return CQR2_ERR_UNSUPPORTED;
-  const GramPlan p = cqr2::plan_gram(m, n);
+  const size_t need = cqr2_gram_workspace_size(m, n);
   if (work == nullptr || ((uintptr_t)work & 7u) != 0) return -7;
-  if (work_bytes < p.partial_bytes) return -8;
+  if (work_bytes < need) return -8;
   const size_t abytes = matrix_bytes(m, n, lda), wbytes = matrix_bytes(n, n, ldw);
   if (overlaps(A, abytes, W, wbytes)) return -5;
   if (overlaps(work, work_bytes, A, abytes) || overlaps(work, work_bytes, W, wbytes)) return -7;
   hipStream_t s = (hipStream_t)stream;
-  // m == 0 runs one workgroup over a fully masked stage and yields W = 0.
-  CQR2_TRY(cqr2::launch_gram_partials(p, A, m, (int)n, lda, (double*)work, nullptr, s));
-  CQR2_TRY(cqr2::launch_gram_reduce(p, (const double*)work, (int)n, W, ldw, nullptr, s));
+  if (n <= kSmallN) {
+    // m == 0 runs one workgroup over a fully masked stage and yields W = 0.
+    const GramPlan p = cqr2::plan_gram(m, n);
+    CQR2_TRY(cqr2::launch_gram_partials(p, A, m, (int)n, lda, (double*)work, nullptr, s));
+    CQR2_TRY(cqr2::launch_gram_reduce(p, (const double*)work, (int)n, W, ldw, nullptr, s));
+    return 0;
+  }
+  // n > 128: lower triangle by the GEMM, then mirrored.
+  const int splits = cqr2::gemm_pick_splits(n, n, m, cqr2::kPlanCUs);
+  CQR2_TRY(cqr2::launch_gemm(1, 0, n, n, m, 1.0, A, lda, A, lda, 0.0, W, ldw, cqr2::GEMM_C_LOWER, splits,
+                             (double*)work, nullptr, s));
+  CQR2_TRY(cqr2::launch_mirror_lower(W, ldw, n, s));
   return 0;
 }
 
@@ -288,8 +324,23 @@ int cqr2_cholinv(const double* W, int64_t n, int64_t ldw, double* R, double* Rin
   if (overlaps(W, wb, R, rb)) return -4;
   if (overlaps(W, wb, Rinv, rb) || overlaps(R, rb, Rinv, rb)) return -5;
   hipStream_t s = (hipStream_t)stream;
-  if (d_info != nullptr) CQR2_TRY(cqr2::launch_set_info(d_info, 0, s));
-  CQR2_TRY(cqr2::launch_cholinv(W, ldw, (int)n, R, ldr, Rinv, ldr, nullptr, 0, d_info, 0, s));
+  if (n <= kSmallN) {
+    if (d_info != nullptr) CQR2_TRY(cqr2::launch_set_info(d_info, 0, s));
+    CQR2_TRY(cqr2::launch_cholinv(W, ldw, (int)n, R, ldr, Rinv, ldr, nullptr, 0, d_info, 0, s));
+    return 0;
+  }
+  // The recursion overwrites the trailing blocks of its input: work on a
+  // copy in the library workspace (info word, W copy, recursion scratch).
+  const size_t wcopy = align_up((size_t)n * n * sizeof(double));
+  int err = 0;
+  char* ws = (char*)cached_workspace(kAlign + wcopy + cqr2::cholinv_rec_workspace(n), &err);
+  if (err) return err;
+  int32_t* info = d_info != nullptr ? d_info : (int32_t*)ws;
+  double* Wc = (double*)(ws + kAlign);
+  CQR2_TRY(cqr2::launch_set_info(info, 0, s));
+  CQR2_TRY(hipMemcpy2DAsync(Wc, n * sizeof(double), W, ldw * sizeof(double), n * sizeof(double), n,
+                            hipMemcpyDeviceToDevice, s));
+  CQR2_TRY(cqr2::cholinv_recursive(Wc, n, n, R, ldr, Rinv, ldr, ws + kAlign + wcopy, info, 0, s));
   return 0;
 }
 
@@ -310,8 +361,24 @@ int cqr2_apply_rinv(const double* A, int64_t m, int64_t n, int64_t lda, const do
   if (in_place && lda != ldq) return -8;
   if (!in_place && overlaps(A, ab, Q, qb)) return -7;
   if (overlaps(U, ub, Q, qb)) return -5;
-  CQR2_TRY(cqr2::launch_apply_rinv(A, m, (int)n, lda, U, 1, ldu, Q, ldq, nullptr, device_cus(),
-                                   (hipStream_t)stream));
+  hipStream_t s = (hipStream_t)stream;
+  if (n <= kSmallN) {
+    CQR2_TRY(cqr2::launch_apply_rinv(A, m, (int)n, lda, U, 1, ldu, Q, ldq, nullptr, device_cus(), s));
+    return 0;
+  }
+  const double* src = A;
+  int64_t lds = lda;
+  if (in_place) {  // the tiled GEMM reads A across output tiles: multiply from a copy
+    int err = 0;
+    double* tmp = (double*)cached_workspace((size_t)m * n * sizeof(double), &err);
+    if (err) return err;
+    CQR2_TRY(hipMemcpy2DAsync(tmp, m * sizeof(double), A, lda * sizeof(double), m * sizeof(double), n,
+                              hipMemcpyDeviceToDevice, s));
+    src = tmp;
+    lds = m;
+  }
+  CQR2_TRY(cqr2::launch_gemm(0, 0, m, n, n, 1.0, src, lds, U, ldu, 0.0, Q, ldq, cqr2::GEMM_B_UPPER, 1, nullptr,
+                             nullptr, s));
   return 0;
 }
 
@@ -324,7 +391,10 @@ int cqr2_upper_product(const double* R2, const double* R1, double* R, int64_t n,
   if (R == nullptr || !aligned8(R)) return -3;
   const size_t b = matrix_bytes(n, n, ld);
   if (overlaps(R, b, R2, b) || overlaps(R, b, R1, b)) return -3;
-  CQR2_TRY(cqr2::launch_upper_product(R2, R1, ld, R, ld, (int)n, nullptr, nullptr, (hipStream_t)stream));
+  hipStream_t s = (hipStream_t)stream;
+  CQR2_TRY(cqr2::launch_gemm(0, 0, n, n, n, 1.0, R2, ld, R1, ld, 0.0, R, ld,
+                             cqr2::GEMM_A_UPPER | cqr2::GEMM_B_UPPER | cqr2::GEMM_C_UPPER, 1, nullptr, nullptr, s));
+  CQR2_TRY(cqr2::launch_finalize_r(R, ld, R, ld, n, nullptr, nullptr, s));
   return 0;
 }
 
@@ -338,6 +408,7 @@ int cqr2_timing_reset(void) {
   std::lock_guard<std::mutex> g(g_timer_mu);
   g_timer.recs.clear();
   g_timer.used = 0;
+  for (auto& o : g_timer.open) o = nullptr;
   return 0;
 }
 

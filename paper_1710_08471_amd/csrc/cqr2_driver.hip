@@ -1,0 +1,203 @@
+// Device-side drivers built from the kernels: the recursive CholInv of
+// Algorithm 2 for any n (base case: the single-workgroup kernel for n <= 128)
+// and CholeskyQR2 (Algorithms 4 and 5) for n > 128 on the general GEMM.
+// Everything is enqueued on one stream; nothing synchronizes with the host.
+#include "cqr2_internal.h"
+
+#include <hip/hip_runtime.h>
+#include <cmath>
+#include <cstdint>
+
+namespace cqr2 {
+
+constexpr int kBaseN = 128;  // largest CholInv handled by one workgroup
+
+int64_t cholinv_split(int64_t n) {
+  // h = largest multiple of the base size not above n/2 (at least one base block)
+  int64_t h = (n / 2) / kBaseN * kBaseN;
+  return h < kBaseN ? kBaseN : h;
+}
+
+// Reduction splits used by every GEMM of the recursion, fixed by the shape only.
+static int rec_splits(int64_t M, int64_t N, int64_t K) { return gemm_pick_splits(M, N, K, kPlanCUs); }
+
+size_t cholinv_rec_workspace(int64_t n) {
+  // scratch T (h x n2 <= n*n/4) + the largest GEMM split workspace of the recursion
+  if (n <= kBaseN) return 0;
+  const int64_t h = cholinv_split(n), n2 = n - h;
+  size_t ws = 0;
+  auto upd = [&](int64_t M, int64_t N, int64_t K) {
+    const size_t b = gemm_workspace_bytes(M, N, rec_splits(M, N, K));
+    ws = b > ws ? b : ws;
+  };
+  upd(h, n2, h);
+  upd(n2, n2, h);
+  upd(h, n2, n2);
+  const size_t inner = cholinv_rec_workspace(h) > cholinv_rec_workspace(n2) ? cholinv_rec_workspace(h)
+                                                                            : cholinv_rec_workspace(n2);
+  const size_t mine = (size_t)h * n2 * sizeof(double) + ws;
+  return mine > inner ? mine : inner;
+}
+
+__global__ void k_zero_block(double* X, int64_t ldx, int64_t rows, int64_t cols) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * cols) return;
+  X[(e % rows) + (e / rows) * ldx] = 0.0;
+}
+
+static hipError_t zero_block(double* X, int64_t ldx, int64_t rows, int64_t cols, hipStream_t s) {
+  const int64_t total = rows * cols;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_block, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, X, ldx, rows, cols);
+  return hipGetLastError();
+}
+
+#define CQR2_HIP(expr)              \
+  do {                              \
+    hipError_t _e = (expr);         \
+    if (_e != hipSuccess) return _e; \
+  } while (0)
+
+// W: n x n (ldw), lower triangle read; its trailing blocks are overwritten by
+// Schur complements.  R, Rinv: n x n upper (ldr, ldri), strictly lower parts 0.
+// work: >= cholinv_rec_workspace(n) bytes.
+hipError_t cholinv_recursive(double* W, int64_t ldw, int64_t n, double* R, int64_t ldr, double* Rinv, int64_t ldri,
+                             char* work, int32_t* info, int info_offset, hipStream_t s) {
+  if (n <= kBaseN) return launch_cholinv(W, ldw, (int)n, R, ldr, Rinv, ldri, nullptr, 0, info, info_offset, s);
+  const int64_t h = cholinv_split(n), n2 = n - h;
+  double* W22 = W + h + h * ldw;
+  double* R12 = R + h * ldr;
+  double* R22 = R + h + h * ldr;
+  double* Ri12 = Rinv + h * ldri;
+  double* Ri22 = Rinv + h + h * ldri;
+  double* T = (double*)work;
+  double* gws = (double*)(work + (size_t)h * n2 * sizeof(double));
+  // L11, Y11 = CholInv(A11)
+  CQR2_HIP(cholinv_recursive(W, ldw, h, R, ldr, Rinv, ldri, work, info, info_offset, s));
+  // L21 = A21 Y11ᵀ, kept as R12 = L21ᵀ = Y11 A21ᵀ = Rinv11ᵀ A21ᵀ
+  CQR2_HIP(launch_gemm(1, 1, h, n2, h, 1.0, Rinv, ldri, W + h, ldw, 0.0, R12, ldr, GEMM_A_LOWER,
+                       rec_splits(h, n2, h), gws, info, s));
+  // A22 - L21 L21ᵀ = A22 - R12ᵀ R12 (lower triangle)
+  CQR2_HIP(launch_gemm(1, 0, n2, n2, h, -1.0, R12, ldr, R12, ldr, 1.0, W22, ldw, GEMM_C_LOWER,
+                       rec_splits(n2, n2, h), gws, info, s));
+  // L22, Y22 = CholInv(A22 - L21 L21ᵀ)
+  CQR2_HIP(cholinv_recursive(W22, ldw, n2, R22, ldr, Ri22, ldri, work, info, info_offset + (int)h, s));
+  // Y21 = -Y22 (L21 Y11): in the transposed factors, Rinv12 = -(Rinv11 R12) Rinv22
+  CQR2_HIP(launch_gemm(0, 0, h, n2, h, 1.0, Rinv, ldri, R12, ldr, 0.0, T, h, GEMM_A_UPPER, rec_splits(h, n2, h), gws,
+                       info, s));
+  CQR2_HIP(launch_gemm(0, 0, h, n2, n2, -1.0, T, h, Ri22, ldri, 0.0, Ri12, ldri, GEMM_B_UPPER,
+                       rec_splits(h, n2, n2), gws, info, s));
+  // strictly lower blocks of the triangular factors
+  CQR2_HIP(zero_block(R + h, ldr, n2, h, s));
+  CQR2_HIP(zero_block(Rinv + h, ldri, n2, h, s));
+  return hipSuccess;
+}
+
+// W(j, i) = W(i, j) for i > j (complete a lower-triangle result).
+__global__ void k_mirror_lower(double* W, int64_t ldw, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * n) return;
+  const int64_t i = e % n, j = e / n;
+  if (i > j) W[j + i * ldw] = W[i + j * ldw];
+}
+
+hipError_t launch_mirror_lower(double* W, int64_t ldw, int64_t n, hipStream_t s) {
+  const int64_t total = n * n;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mirror_lower, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, W, ldw, n);
+  return hipGetLastError();
+}
+
+// R = upper triangle of P (n x n) with zeros below; NaN everywhere after a
+// breakdown; publish the info word.
+// P may equal R (in place: each thread reads and writes one element).
+__global__ __launch_bounds__(256) void k_finalize_r(const double* P, int64_t ldp, double* R, int64_t ldr, int64_t n,
+                                                    const int32_t* info, int32_t* user_info) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int32_t st = info != nullptr ? *info : 0;
+  if (e == 0 && user_info != nullptr) *user_info = st;
+  if (e >= n * n) return;
+  const int64_t i = e % n, j = e / n;
+  R[i + j * ldr] = st != 0 ? __builtin_nan("") : (i <= j ? P[i + j * ldp] : 0.0);
+}
+
+hipError_t launch_finalize_r(const double* P, int64_t ldp, double* R, int64_t ldr, int64_t n, const int32_t* info,
+                             int32_t* user_info, hipStream_t s) {
+  const int64_t total = n * n;
+  hipLaunchKernelGGL(k_finalize_r, dim3((unsigned)((total + 255) / 256 > 0 ? (total + 255) / 256 : 1)), dim3(256),
+                     0, s, P, ldp, R, ldr, n, info, user_info);
+  return hipGetLastError();
+}
+
+// ---- CholeskyQR2 for n > 128 ------------------------------------------------
+GeneralPlan plan_general(int64_t m, int64_t n) {
+  GeneralPlan p{};
+  p.gram_splits = gemm_pick_splits(n, n, m, kPlanCUs);
+  p.apply_splits = 1;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) / 256 * 256;
+    return o;
+  };
+  const size_t nn = (size_t)n * n * sizeof(double);
+  p.off_info = take(16);
+  p.off_w = take(nn);
+  p.off_r1 = take(nn);
+  p.off_ri1 = take(nn);
+  p.off_r2 = take(nn);
+  p.off_ri2 = take(nn);
+  p.off_p = take(nn);
+  const size_t gws = gemm_workspace_bytes(n, n, p.gram_splits);
+  const size_t rws = cholinv_rec_workspace(n);
+  p.off_scratch = take(gws > rws ? gws : rws);
+  p.off_q1 = take((size_t)m * n * sizeof(double));
+  p.total = off;
+  return p;
+}
+
+hipError_t factor_general(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, int64_t ldq, double* R,
+                          int64_t ldr, char* ws, const GeneralPlan& p, int32_t* d_info, hipStream_t s,
+                          const TimerHook& th) {
+  int32_t* info = (int32_t*)(ws + p.off_info);
+  double* W = (double*)(ws + p.off_w);
+  double* R1 = (double*)(ws + p.off_r1);
+  double* Ri1 = (double*)(ws + p.off_ri1);
+  double* R2 = (double*)(ws + p.off_r2);
+  double* Ri2 = (double*)(ws + p.off_ri2);
+  double* P = (double*)(ws + p.off_p);
+  char* scratch = ws + p.off_scratch;
+  double* Q1 = (double*)(ws + p.off_q1);
+  CQR2_HIP(launch_set_info(info, 0, s));
+  // pass 1: CQR(A) -> Q1 (workspace), R1
+  th.begin(0, s);
+  CQR2_HIP(launch_gemm(1, 0, n, n, m, 1.0, A, lda, A, lda, 0.0, W, n, GEMM_C_LOWER, p.gram_splits, (double*)scratch,
+                       info, s));
+  th.end(0, s);
+  th.begin(2, s);
+  CQR2_HIP(cholinv_recursive(W, n, n, R1, n, Ri1, n, scratch, info, 0, s));
+  th.end(2, s);
+  th.begin(3, s);
+  CQR2_HIP(launch_gemm(0, 0, m, n, n, 1.0, A, lda, Ri1, n, 0.0, Q1, m, GEMM_B_UPPER, 1, nullptr, info, s));
+  th.end(3, s);
+  // pass 2: CQR(Q1) -> Q, R2
+  th.begin(0, s);
+  CQR2_HIP(launch_gemm(1, 0, n, n, m, 1.0, Q1, m, Q1, m, 0.0, W, n, GEMM_C_LOWER, p.gram_splits, (double*)scratch,
+                       info, s));
+  th.end(0, s);
+  th.begin(2, s);
+  CQR2_HIP(cholinv_recursive(W, n, n, R2, n, Ri2, n, scratch, info, (int)n, s));
+  th.end(2, s);
+  th.begin(4, s);
+  CQR2_HIP(launch_gemm(0, 0, m, n, n, 1.0, Q1, m, Ri2, n, 0.0, Q, ldq, GEMM_B_UPPER, 1, nullptr, info, s));
+  th.end(4, s);
+  // R = R2 R1
+  th.begin(5, s);
+  CQR2_HIP(launch_gemm(0, 0, n, n, n, 1.0, R2, n, R1, n, 0.0, P, n, GEMM_A_UPPER | GEMM_B_UPPER | GEMM_C_UPPER, 1,
+                       nullptr, info, s));
+  CQR2_HIP(launch_finalize_r(P, n, R, ldr, n, info, d_info, s));
+  th.end(5, s);
+  return hipSuccess;
+}
+
+}  // namespace cqr2

@@ -7,6 +7,22 @@
 
 namespace cqr2 {
 
+// Planning never depends on the device: splits and workspace layouts are a
+// function of the problem shape alone, so results are bit-identical on any GPU.
+constexpr int kPlanCUs = 256;
+
+// Optional per-kernel-class timing around launches (set by the C ABI layer).
+struct TimerHook {
+  void (*b)(int, hipStream_t) = nullptr;
+  void (*e)(int, hipStream_t) = nullptr;
+  void begin(int c, hipStream_t s) const {
+    if (b) b(c, s);
+  }
+  void end(int c, hipStream_t s) const {
+    if (e) e(c, s);
+  }
+};
+
 // ---- Gram (Syrk) -----------------------------------------------------------
 struct GramPlan {
   int ng;        // 4-column groups the kernel instance covers (power of two, >= ceil(n/4))
@@ -43,9 +59,46 @@ hipError_t launch_cholinv(const double* W, int64_t ldw, int n, double* R, int64_
 hipError_t launch_apply_rinv(const double* A, int64_t m, int n, int64_t lda, const double* U, int64_t urs,
                              int64_t ucs, double* Q, int64_t ldq, const int32_t* info, int num_cus, hipStream_t s);
 
-// ---- R = R2 R1 -------------------------------------------------------------
-hipError_t launch_upper_product(const double* R2, const double* R1, int64_t ldin, double* R, int64_t ldr,
-                                int n, const int32_t* info, int32_t* user_info, hipStream_t s);
+// ---- general FP64 GEMM: C = alpha op(A) op(B) + beta C ----------------------
+enum GemmFlags {
+  GEMM_A_LOWER = 1,  // op(A)(i, k) == 0 for k > i
+  GEMM_A_UPPER = 2,  // op(A)(i, k) == 0 for k < i
+  GEMM_B_LOWER = 4,  // op(B)(k, j) == 0 for k < j
+  GEMM_B_UPPER = 8,  // op(B)(k, j) == 0 for k > j
+  GEMM_C_LOWER = 16, // only C(i, j), i >= j, is computed and written
+  GEMM_C_UPPER = 32, // only C(i, j), i <= j
+};
+// Reduction splits for a problem shape (1 = no split).
+int gemm_pick_splits(int64_t M, int64_t N, int64_t K, int num_cus);
+size_t gemm_workspace_bytes(int64_t M, int64_t N, int splits);
+// splits > 1 needs work >= gemm_workspace_bytes(M, N, splits).
+hipError_t launch_gemm(int transA, int transB, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
+                       int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int flags,
+                       int splits, double* work, const int32_t* info, hipStream_t s);
+
+// ---- recursive CholInv and the n > 128 driver --------------------------------
+int64_t cholinv_split(int64_t n);
+size_t cholinv_rec_workspace(int64_t n);
+// W (n x n, ldw, lower read, trailing blocks overwritten) -> R, Rinv upper.
+hipError_t cholinv_recursive(double* W, int64_t ldw, int64_t n, double* R, int64_t ldr, double* Rinv, int64_t ldri,
+                             char* work, int32_t* info, int info_offset, hipStream_t s);
+// R = triu(P), or NaN after a breakdown; copies the info word to user_info.
+hipError_t launch_finalize_r(const double* P, int64_t ldp, double* R, int64_t ldr, int64_t n, const int32_t* info,
+                             int32_t* user_info, hipStream_t s);
+
+// W(j, i) = W(i, j) for i > j.
+hipError_t launch_mirror_lower(double* W, int64_t ldw, int64_t n, hipStream_t s);
+
+struct GeneralPlan {
+  int gram_splits = 1, apply_splits = 1;
+  size_t off_info = 0, off_w = 0, off_r1 = 0, off_ri1 = 0, off_r2 = 0, off_ri2 = 0, off_p = 0, off_scratch = 0,
+         off_q1 = 0;
+  size_t total = 0;
+};
+GeneralPlan plan_general(int64_t m, int64_t n);
+hipError_t factor_general(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, int64_t ldq, double* R,
+                          int64_t ldr, char* ws, const GeneralPlan& p, int32_t* d_info, hipStream_t s,
+                          const TimerHook& th);
 
 // ---- small helpers ---------------------------------------------------------
 hipError_t launch_set_info(int32_t* info, int32_t value, hipStream_t s);

@@ -2,7 +2,6 @@
 //   Gram  W = AᵀA              (paper: Syrk, Section "Preliminaries"; Algorithm 4 step 1)
 //   CholInv(W) -> R, R^{-1}    (Algorithm 2)
 //   Q = A R^{-1}               (Algorithm 4 step 3, MM with an upper-triangular right factor)
-//   R = R2 R1                  (Algorithm 5, last step)
 // All arithmetic is IEEE FP64.  Reductions use fixed orders (no FP atomics),
 // so results are bit-reproducible for a given (m, n, lda, device).
 #include "cqr2_internal.h"
@@ -715,36 +714,6 @@ hipError_t launch_apply_rinv(const double* A, int64_t m, int n, int64_t lda, con
       break;
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
-}
-
-// ============================================================================
-// R = R2 R1 for upper-triangular factors; one thread per entry, ascending k.
-// Also publishes the device info word and NaN-fills R after a breakdown.
-// ============================================================================
-__global__ __launch_bounds__(256) void k_upper_product(const double* __restrict__ R2, const double* __restrict__ R1,
-                                                       int64_t ldin, double* __restrict__ R, int64_t ldr, int n,
-                                                       const int32_t* __restrict__ info,
-                                                       int32_t* __restrict__ user_info) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int32_t st = info != nullptr ? *info : 0;
-  if (e == 0 && user_info != nullptr) *user_info = st;
-  if (e >= (int64_t)n * n) return;
-  const int i = (int)(e % n), j = (int)(e / n);
-  double v = 0.0;
-  if (st != 0) {
-    v = __builtin_nan("");
-  } else if (i <= j) {
-    for (int k = i; k <= j; ++k) v = fma(R2[i + (int64_t)k * ldin], R1[k + (int64_t)j * ldin], v);
-  }
-  R[i + (int64_t)j * ldr] = v;
-}
-
-hipError_t launch_upper_product(const double* R2, const double* R1, int64_t ldin, double* R, int64_t ldr,
-                                int n, const int32_t* info, int32_t* user_info, hipStream_t s) {
-  const int64_t total = (int64_t)n * n;
-  dim3 grid((unsigned)((total + 255) / 256 > 0 ? (total + 255) / 256 : 1));
-  hipLaunchKernelGGL(k_upper_product, grid, dim3(256), 0, s, R2, R1, ldin, R, ldr, n, info, user_info);
   return hipGetLastError();
 }
 

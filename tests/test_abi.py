@@ -58,7 +58,7 @@ def test_factor_argument_errors():
     assert f(FAKE, 10, 5, 10, FAKE2, NULL, NULL) == -6              # R NULL
     assert f(ctypes.c_void_p(0x10004), 10, 5, 10, FAKE2, FAKE2, NULL) == -1   # misaligned
     assert f(FAKE, 10, 5, 10, ctypes.c_void_p(0x10000 + 80), FAKE2, NULL) == -5  # Q overlaps A
-    assert f(FAKE, 1000, 200, 1000, FAKE2, ctypes.c_void_p(0x20000000), NULL) == cq.CQR2_ERR_UNSUPPORTED
+    assert f(FAKE, 40000, 20000, 40000, FAKE2, ctypes.c_void_p(0x20000000), NULL) == cq.CQR2_ERR_UNSUPPORTED
     assert f(NULL, 10, 0, 10, NULL, NULL, NULL) == 0                # n == 0: quick return
 
 
@@ -91,7 +91,8 @@ def test_workspace_size_contract():
     lib = cq.load()
     assert lib.cqr2_workspace_size(10, 20, 0) == 0       # m < n
     assert lib.cqr2_workspace_size(100, 0, 0) == 0
-    assert lib.cqr2_workspace_size(100, 129, 0) == 0     # beyond the tall-skinny limit
+    assert lib.cqr2_workspace_size(40000, 20000, 0) == 0  # beyond CQR2_MAX_N
+    assert lib.cqr2_workspace_size(1000, 200, 0) > 0      # general (tiled) path
     small = lib.cqr2_workspace_size(4096, 64, 0)
     big = lib.cqr2_workspace_size(1 << 20, 128, 0)
     assert 0 < small < big

@@ -153,3 +153,32 @@ def test_factor_integer_orthogonal_columns_exact(gpu_lib):
     nrm = np.sqrt(1024.0)
     assert np.array_equal(r, np.diag(np.array([1.0, 2.0, 4.0, 0.5]) * nrm))
     assert np.array_equal(q, a / (np.array([1.0, 2.0, 4.0, 0.5]) * nrm))
+
+
+@pytest.mark.parametrize("m,n,kappa,seed", [
+    (2000, 129, 1e3, 31), (10000, 200, 1e5, 32), (30000, 256, 1e6, 33), (1500, 300, 1e4, 34),
+    (256, 256, 1e2, 35), (4096, 520, 1e3, 36)])
+def test_factor_wide_matches_oracle(gpu_lib, m, n, kappa, seed):
+    a = gdv_matrix(m, n, kappa, seed)
+    q_ref, r_ref = oracle.cqr2(a)
+    qd, rd = gpu_lib.factor(to_dev(a))
+    check_against_oracle(a, to_host(qd), to_host(rd), q_ref, r_ref, kappa)
+
+
+def test_factor_wide_breakdown(gpu_lib):
+    import torch
+    a = gdv_matrix(3000, 256, 10.0, 37)
+    a[:, 200] = 0.0
+    info = torch.zeros((1,), dtype=torch.int32, device="cuda")
+    q, r = gpu_lib.factor_ex(to_dev(a), info=info)
+    assert int(info.item()) == 201
+    assert np.all(np.isnan(to_host(r)))
+
+
+def test_factor_wide_deterministic(gpu_lib):
+    a = gdv_matrix(20000, 256, 1e4, 38)
+    ad = to_dev(a)
+    q1, r1 = gpu_lib.factor(ad)
+    q2, r2 = gpu_lib.factor(ad)
+    assert np.array_equal(to_host(q1), to_host(q2))
+    assert np.array_equal(to_host(r1), to_host(r2))

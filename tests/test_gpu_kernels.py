@@ -174,3 +174,62 @@ def test_upper_product_float_bound(gpu_lib):
     bound = 2 * gamma(n) * (np.abs(r2) @ np.abs(r1))
     assert np.all(np.abs(r - r2 @ r1) <= bound)
     assert np.array_equal(r, np.triu(r))
+
+
+# ------------------------------------------------- n > 128 (tiled path) ---
+
+@pytest.mark.parametrize("m,n", [(1000, 129), (5003, 200), (20000, 256), (777, 300)])
+def test_gram_wide_integer_exact(gpu_lib, m, n):
+    a = integer_matrix(m, n, 1 << 8, seed=m + n)
+    w = to_host(gpu_lib.gram(to_dev(a)))
+    assert np.array_equal(w, oracle.syrk(a))
+
+
+@pytest.mark.parametrize("m,n", [(300, 129), (1000, 200), (4099, 256), (513, 300)])
+def test_apply_rinv_wide_integer_exact(gpu_lib, m, n):
+    a = integer_matrix(m, n, 8, seed=m)
+    u = _int_upper(n, seed=n, mx=8)
+    q = to_host(gpu_lib.apply_rinv(to_dev(a), to_dev(u)))
+    assert np.array_equal(q, a @ u)
+    ad = to_dev(a)
+    gpu_lib.apply_rinv(ad, to_dev(u), Q=ad)      # in place
+    assert np.array_equal(to_host(ad), a @ u)
+
+
+@pytest.mark.parametrize("n", [129, 200, 256])
+def test_upper_product_wide_integer_exact(gpu_lib, n):
+    r2 = _int_upper(n, seed=1 + n, mx=16)
+    r1 = _int_upper(n, seed=2 + n, mx=16)
+    r = to_host(gpu_lib.upper_product(to_dev(r2), to_dev(r1)))
+    assert np.array_equal(r, oracle.upper_product(r2, r1))
+
+
+@pytest.mark.parametrize("n,kappa", [(129, 1e2), (200, 1e3), (256, 1e3), (300, 1e2), (520, 1e2)])
+def test_cholinv_recursive_random_spd(gpu_lib, n, kappa):
+    a = gdv_matrix(2 * n + 7, n, kappa, seed=n)
+    w = oracle.syrk(a)
+    l_ref, y_ref = oracle.cholinv(w)
+    wd = to_dev(w)
+    r, rinv = gpu_lib.cholinv(wd)
+    r, rinv = to_host(r), to_host(rinv)
+    assert np.array_equal(to_host(wd), w)          # input untouched
+    cw = np.linalg.cond(w)
+    tol = 20 * n * U64 * cw
+    assert oracle.rel_fro(r, l_ref.T) <= tol
+    assert oracle.rel_fro(rinv, y_ref.T) <= tol
+    assert np.array_equal(r, np.triu(r)) and np.array_equal(rinv, np.triu(rinv))
+    assert np.all(np.diag(r) > 0)
+    assert np.linalg.norm(r.T @ r - w) <= 10 * n * U64 * np.linalg.norm(w)
+
+
+@pytest.mark.parametrize("j", [3, 150, 255])
+def test_cholinv_recursive_breakdown(gpu_lib, j):
+    import torch
+    n = 256
+    a = gdv_matrix(600, n, 10.0, seed=4)
+    w = oracle.syrk(a)
+    w[j, :] = 0.0
+    w[:, j] = 0.0
+    info = torch.zeros((1,), dtype=torch.int32, device="cuda")
+    gpu_lib.cholinv(to_dev(w), info=info)
+    assert int(info.item()) == j + 1
