@@ -46,9 +46,13 @@ extern "C" {
 
 /* flags */
 #define CQR2_FP64 0u
-/* Pass 1's Q1 = A R1^{-1} in FP32 arithmetic with an FP32 Q1 in the workspace
- * (Gram, CholInv and pass 2 stay FP64).  Reduced precision: orthogonality is
- * recovered by pass 2, the residual is at the FP32 rounding level. */
+/* Pass 1's Q1 = A R1^{-1} in FP32 arithmetic (A and R1^{-1} rounded to FP32,
+ * FP32 MFMA products and sums) with an FP32 Q1 of m*n*4 bytes in the
+ * workspace; the Gram matrices, CholInv and all of pass 2 stay FP64, and pass 2
+ * factors the stored FP32 Q1 widened exactly.  Orthogonality is recovered by
+ * pass 2 (the FP64 gate holds); the residual ||A - QR||/||A|| and R are
+ * accurate to the FP32 rounding level only.  Runs the tiled path at every n.
+ * Accepted by cqr2_factor_ex / cqr2_workspace_size. */
 #define CQR2_MIXED_P1_FP32 1u
 
 /* Largest n accepted (every n x n workspace block is n*n*8 bytes).  Up to

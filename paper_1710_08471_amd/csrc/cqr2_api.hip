@@ -69,8 +69,13 @@ SmallLayout make_small_layout(int64_t m, int64_t n) {
   return L;
 }
 
-size_t factor_workspace(int64_t m, int64_t n) {
-  return n <= kSmallN ? make_small_layout(m, n).total : cqr2::plan_general(m, n).total;
+// FP64 factorizations with n <= 128 run the tall-skinny kernels; everything
+// else (n > 128, and the mixed-precision form at any n) runs the tiled path.
+bool use_small(int64_t n, uint32_t flags) { return n <= kSmallN && flags == CQR2_FP64; }
+
+size_t factor_workspace(int64_t m, int64_t n, uint32_t flags) {
+  return use_small(n, flags) ? make_small_layout(m, n).total
+                             : cqr2::plan_general(m, n, flags == CQR2_MIXED_P1_FP32).total;
 }
 
 // ---- timing instrumentation -------------------------------------------------
@@ -194,11 +199,12 @@ int run_small(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, int
 }
 
 int run_factor(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, int64_t ldq, double* R, int64_t ldr,
-               char* ws, int32_t* d_info, hipStream_t s) {
-  if (n <= kSmallN)
+               char* ws, int32_t* d_info, uint32_t flags, hipStream_t s) {
+  if (use_small(n, flags))
     return run_small(A, m, n, lda, Q, ldq, R, ldr, ws, make_small_layout(m, n), d_info, s, device_cus());
-  const cqr2::GeneralPlan p = cqr2::plan_general(m, n);
-  return check_hip(cqr2::factor_general(A, m, n, lda, Q, ldq, R, ldr, ws, p, d_info, s, timer_hook()));
+  const bool mixed = flags == CQR2_MIXED_P1_FP32;
+  const cqr2::GeneralPlan p = cqr2::plan_general(m, n, mixed);
+  return check_hip(cqr2::factor_general(A, m, n, lda, Q, ldq, R, ldr, ws, p, mixed, d_info, s, timer_hook()));
 }
 
 }  // namespace
@@ -219,8 +225,8 @@ const char* cqr2_status_string(int code) {
 }
 
 size_t cqr2_workspace_size(int64_t m, int64_t n, uint32_t flags) {
-  if (m < n || n < 1 || flags != CQR2_FP64 || n > CQR2_MAX_N) return 0;
-  return factor_workspace(m, n);
+  if (m < n || n < 1 || (flags != CQR2_FP64 && flags != CQR2_MIXED_P1_FP32) || n > CQR2_MAX_N) return 0;
+  return factor_workspace(m, n, flags);
 }
 
 int cqr2_factor_ex(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, int64_t ldq, double* R,
@@ -232,7 +238,7 @@ int cqr2_factor_ex(const double* A, int64_t m, int64_t n, int64_t lda, double* Q
   if (lda < (m > 1 ? m : 1)) return -4;
   if (ldq < (m > 1 ? m : 1)) return -6;
   if (ldr < (n > 1 ? n : 1)) return -8;
-  if (flags != CQR2_FP64) return -12;
+  if (flags != CQR2_FP64 && flags != CQR2_MIXED_P1_FP32) return -12;
   if (n == 0) return 0;
   if (A == nullptr || !aligned8(A)) return -1;
   if (Q == nullptr || !aligned8(Q)) return -5;
@@ -242,14 +248,14 @@ int cqr2_factor_ex(const double* A, int64_t m, int64_t n, int64_t lda, double* Q
   if (overlaps(A, abytes, Q, qbytes)) return -5;
   if (overlaps(A, abytes, R, rbytes)) return -7;
   if (overlaps(Q, qbytes, R, rbytes)) return -7;
-  const size_t need = factor_workspace(m, n);
+  const size_t need = factor_workspace(m, n, flags);
   if (work == nullptr || ((uintptr_t)work % kAlign) != 0) return -9;
   if (work_bytes < need) return -10;
   if (overlaps(work, work_bytes, A, abytes) || overlaps(work, work_bytes, Q, qbytes) ||
       overlaps(work, work_bytes, R, rbytes))
     return -9;
   if (d_info != nullptr && ((uintptr_t)d_info & 3u) != 0) return -11;
-  return run_factor(A, m, n, lda, Q, ldq, R, ldr, (char*)work, d_info, (hipStream_t)stream);
+  return run_factor(A, m, n, lda, Q, ldq, R, ldr, (char*)work, d_info, flags, (hipStream_t)stream);
 }
 
 int cqr2_factor(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, double* R, void* stream) {
@@ -265,9 +271,9 @@ int cqr2_factor(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, d
   if (overlaps(A, abytes, Q, abytes)) return -5;
   if (overlaps(A, abytes, R, rbytes) || overlaps(Q, abytes, R, rbytes)) return -6;
   int err = 0;
-  void* ws = cached_workspace(factor_workspace(m, n), &err);
+  void* ws = cached_workspace(factor_workspace(m, n, CQR2_FP64), &err);
   if (err) return err;
-  return run_factor(A, m, n, lda, Q, lda, R, n, (char*)ws, nullptr, (hipStream_t)stream);
+  return run_factor(A, m, n, lda, Q, lda, R, n, (char*)ws, nullptr, CQR2_FP64, (hipStream_t)stream);
 }
 
 size_t cqr2_gram_workspace_size(int64_t m, int64_t n) {

@@ -130,7 +130,7 @@ hipError_t launch_finalize_r(const double* P, int64_t ldp, double* R, int64_t ld
 }
 
 // ---- CholeskyQR2 for n > 128 ------------------------------------------------
-GeneralPlan plan_general(int64_t m, int64_t n) {
+GeneralPlan plan_general(int64_t m, int64_t n, bool mixed) {
   GeneralPlan p{};
   p.gram_splits = gemm_pick_splits(n, n, m, kPlanCUs);
   p.apply_splits = 1;
@@ -151,13 +151,13 @@ GeneralPlan plan_general(int64_t m, int64_t n) {
   const size_t gws = gemm_workspace_bytes(n, n, p.gram_splits);
   const size_t rws = cholinv_rec_workspace(n);
   p.off_scratch = take(gws > rws ? gws : rws);
-  p.off_q1 = take((size_t)m * n * sizeof(double));
+  p.off_q1 = take((size_t)m * n * (mixed ? sizeof(float) : sizeof(double)));
   p.total = off;
   return p;
 }
 
 hipError_t factor_general(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, int64_t ldq, double* R,
-                          int64_t ldr, char* ws, const GeneralPlan& p, int32_t* d_info, hipStream_t s,
+                          int64_t ldr, char* ws, const GeneralPlan& p, bool mixed, int32_t* d_info, hipStream_t s,
                           const TimerHook& th) {
   int32_t* info = (int32_t*)(ws + p.off_info);
   double* W = (double*)(ws + p.off_w);
@@ -167,7 +167,8 @@ hipError_t factor_general(const double* A, int64_t m, int64_t n, int64_t lda, do
   double* Ri2 = (double*)(ws + p.off_ri2);
   double* P = (double*)(ws + p.off_p);
   char* scratch = ws + p.off_scratch;
-  double* Q1 = (double*)(ws + p.off_q1);
+  void* Q1 = ws + p.off_q1;
+  const int q1f = mixed ? 1 : 0;  // element type of the stored Q1
   CQR2_HIP(launch_set_info(info, 0, s));
   // pass 1: CQR(A) -> Q1 (workspace), R1
   th.begin(0, s);
@@ -178,18 +179,22 @@ hipError_t factor_general(const double* A, int64_t m, int64_t n, int64_t lda, do
   CQR2_HIP(cholinv_recursive(W, n, n, R1, n, Ri1, n, scratch, info, 0, s));
   th.end(2, s);
   th.begin(3, s);
-  CQR2_HIP(launch_gemm(0, 0, m, n, n, 1.0, A, lda, Ri1, n, 0.0, Q1, m, GEMM_B_UPPER, 1, nullptr, info, s));
+  if (mixed)
+    CQR2_HIP(launch_gemm_f32(0, 0, m, n, n, A, lda, Ri1, n, (float*)Q1, m, GEMM_B_UPPER, info, s));
+  else
+    CQR2_HIP(launch_gemm(0, 0, m, n, n, 1.0, A, lda, Ri1, n, 0.0, (double*)Q1, m, GEMM_B_UPPER, 1, nullptr, info, s));
   th.end(3, s);
-  // pass 2: CQR(Q1) -> Q, R2
+  // pass 2: CQR(Q1) -> Q, R2, on the stored Q1 values (FP32 ones widen exactly)
   th.begin(0, s);
-  CQR2_HIP(launch_gemm(1, 0, n, n, m, 1.0, Q1, m, Q1, m, 0.0, W, n, GEMM_C_LOWER, p.gram_splits, (double*)scratch,
-                       info, s));
+  CQR2_HIP(launch_gemm_in32(q1f, q1f, 1, 0, n, n, m, 1.0, Q1, m, Q1, m, 0.0, W, n, GEMM_C_LOWER, p.gram_splits,
+                            (double*)scratch, info, s));
   th.end(0, s);
   th.begin(2, s);
   CQR2_HIP(cholinv_recursive(W, n, n, R2, n, Ri2, n, scratch, info, (int)n, s));
   th.end(2, s);
   th.begin(4, s);
-  CQR2_HIP(launch_gemm(0, 0, m, n, n, 1.0, Q1, m, Ri2, n, 0.0, Q, ldq, GEMM_B_UPPER, 1, nullptr, info, s));
+  CQR2_HIP(launch_gemm_in32(q1f, 0, 0, 0, m, n, n, 1.0, Q1, m, Ri2, n, 0.0, Q, ldq, GEMM_B_UPPER, 1, nullptr, info,
+                            s));
   th.end(4, s);
   // R = R2 R1
   th.begin(5, s);

@@ -33,11 +33,11 @@ __device__ __forceinline__ int bs_pos(int k, int c) { return k * kGN + c; }
 
 struct GemmArgs {
   int64_t M, N, K;
-  const double* A;
+  const void* A;     // element type per kernel instance (double or float)
   int64_t lda;
-  const double* B;
+  const void* B;
   int64_t ldb;
-  double* C;
+  void* C;           // double, or float for the FP32-arithmetic instance
   int64_t ldc;
   double alpha, beta;
   int transA, transB;
@@ -49,13 +49,33 @@ struct GemmArgs {
   const int32_t* info; // optional: skip when *info != 0
 };
 
+template <typename TA>
 __device__ __forceinline__ double load_opA(const GemmArgs& g, int64_t i, int64_t k) {
-  return g.transA ? g.A[k + i * g.lda] : g.A[i + k * g.lda];
+  const TA* A = (const TA*)g.A;
+  return (double)(g.transA ? A[k + i * g.lda] : A[i + k * g.lda]);
 }
+template <typename TB>
 __device__ __forceinline__ double load_opB(const GemmArgs& g, int64_t k, int64_t j) {
-  return g.transB ? g.B[j + k * g.ldb] : g.B[k + j * g.ldb];
+  const TB* B = (const TB*)g.B;
+  return (double)(g.transB ? B[j + k * g.ldb] : B[k + j * g.ldb]);
 }
 
+// Reduction range of output tile (i0, j0) for split `split` (triangular operands).
+__device__ __forceinline__ void gemm_krange(const GemmArgs& g, int64_t i0, int64_t j0, int split, int64_t& kb,
+                                            int64_t& ke) {
+  kb = 0;
+  ke = g.K;
+  if (g.flags & GEMM_A_LOWER) ke = ke < i0 + 64 ? ke : i0 + 64;   // op(A)(i,k) = 0 for k > i
+  if (g.flags & GEMM_A_UPPER) kb = kb > i0 ? kb : i0;             // op(A)(i,k) = 0 for k < i
+  if (g.flags & GEMM_B_UPPER) ke = ke < j0 + 64 ? ke : j0 + 64;   // op(B)(k,j) = 0 for k > j
+  if (g.flags & GEMM_B_LOWER) kb = kb > j0 ? kb : j0;             // op(B)(k,j) = 0 for k < j
+  const int64_t sb = (int64_t)split * g.kchunk, se = sb + g.kchunk;
+  kb = kb > sb ? kb : sb;
+  ke = ke < se ? ke : se;
+  kb = (kb / 16) * 16;  // chunk-aligned start (entries below kb are zero by structure)
+}
+
+template <typename TA, typename TB>
 __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
   __shared__ double As[2][kGK * kGM];
   __shared__ double Bs[2][kGK * kGN];
@@ -65,16 +85,8 @@ __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
   // Output tiles entirely outside the requested triangle of C.
   if ((g.flags & GEMM_C_LOWER) && i0 + kGM <= j0) return;
   if ((g.flags & GEMM_C_UPPER) && j0 + kGN <= i0) return;
-  // Reduction range of this tile (triangular operands) intersected with the split.
-  int64_t kb = 0, ke = g.K;
-  if (g.flags & GEMM_A_LOWER) ke = ke < i0 + kGM ? ke : i0 + kGM;   // op(A)(i,k) = 0 for k > i
-  if (g.flags & GEMM_A_UPPER) kb = kb > i0 ? kb : i0;              // op(A)(i,k) = 0 for k < i
-  if (g.flags & GEMM_B_UPPER) ke = ke < j0 + kGN ? ke : j0 + kGN;   // op(B)(k,j) = 0 for k > j
-  if (g.flags & GEMM_B_LOWER) kb = kb > j0 ? kb : j0;              // op(B)(k,j) = 0 for k < j
-  const int64_t sb = (int64_t)split * g.kchunk, se = sb + g.kchunk;
-  kb = kb > sb ? kb : sb;
-  ke = ke < se ? ke : se;
-  kb = (kb / kGK) * kGK;  // chunk-aligned start (entries below kb are zero by structure)
+  int64_t kb, ke;
+  gemm_krange(g, i0, j0, split, kb, ke);
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;  // wave tile origin within the block
@@ -89,11 +101,11 @@ __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
       int r, k;
       if (g.transA) { k = e & 15; r = e >> 4; } else { r = e & 63; k = e >> 6; }
       const int64_t gi = i0 + r, gk = k0 + k;
-      ra[t] = (gi < g.M && gk < ke) ? load_opA(g, gi, gk) : 0.0;
+      ra[t] = (gi < g.M && gk < ke) ? load_opA<TA>(g, gi, gk) : 0.0;
       int kk, c;
       if (g.transB) { c = e & 63; kk = e >> 6; } else { kk = e & 15; c = e >> 4; }
       const int64_t bk = k0 + kk, gj = j0 + c;
-      rb[t] = (gj < g.N && bk < ke) ? load_opB(g, bk, gj) : 0.0;
+      rb[t] = (gj < g.N && bk < ke) ? load_opB<TB>(g, bk, gj) : 0.0;
     }
   };
   auto sstore = [&](int buf) {
@@ -154,7 +166,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
         g.partial[(int64_t)split * g.ldp * g.N + i + j * g.ldp] = acc[rt][cg];
       } else {
         const double v = g.alpha * acc[rt][cg];
-        double* cp = g.C + i + j * g.ldc;
+        double* cp = (double*)g.C + i + j * g.ldc;
         *cp = (g.beta == 0.0) ? v : v + g.beta * *cp;
       }
     }
@@ -172,8 +184,92 @@ __global__ __launch_bounds__(256) void k_gemm_reduce(GemmArgs g) {
   double s = 0.0;
   for (int t = 0; t < g.splits; ++t) s += g.partial[(int64_t)t * g.ldp * g.N + i + j * g.ldp];
   const double v = g.alpha * s;
-  double* cp = g.C + i + j * g.ldc;
+  double* cp = (double*)g.C + i + j * g.ldc;
   *cp = (g.beta == 0.0) ? v : v + g.beta * *cp;
+}
+
+// ---- FP32 arithmetic: C(float) = op(A) op(B) with A, B rounded to FP32 ------
+// v_mfma_f32_16x16x4_f32, per lane l: A operand (row l%16, k l/16), B operand
+// (k l/16, column l%16), result entry r: (row 4(l/16) + r, column l%16).  A
+// workgroup computes a 64 x 64 tile (waves 2 x 2, each 2 x 2 MFMA tiles);
+// products and sums are FP32 (no split of the reduction).
+__global__ __launch_bounds__(256, 2) void k_gemm_f32(GemmArgs g) {
+  __shared__ float As[2][kGK * kGM];
+  __shared__ float Bs[2][kGK * kGN];
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  if (g.info != nullptr && *g.info != 0) return;
+  const int64_t i0 = (int64_t)blockIdx.x * kGM, j0 = (int64_t)blockIdx.y * kGN;
+  int64_t kb, ke;
+  gemm_krange(g, i0, j0, 0, kb, ke);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
+  float ra[4], rb[4];
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int e = tid + 256 * t;
+      int r, k;
+      if (g.transA) { k = e & 15; r = e >> 4; } else { r = e & 63; k = e >> 6; }
+      const int64_t gi = i0 + r, gk = k0 + k;
+      ra[t] = (gi < g.M && gk < ke) ? (float)load_opA<double>(g, gi, gk) : 0.0f;
+      int kk, c;
+      if (g.transB) { c = e & 63; kk = e >> 6; } else { kk = e & 15; c = e >> 4; }
+      const int64_t bk = k0 + kk, gj = j0 + c;
+      rb[t] = (gj < g.N && bk < ke) ? (float)load_opB<double>(g, bk, gj) : 0.0f;
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int e = tid + 256 * t;
+      int r, k;
+      if (g.transA) { k = e & 15; r = e >> 4; } else { r = e & 63; k = e >> 6; }
+      As[buf][as_pos(k, r)] = ra[t];
+      int kk, c;
+      if (g.transB) { c = e & 63; kk = e >> 6; } else { kk = e & 15; c = e >> 4; }
+      Bs[buf][bs_pos(kk, c)] = rb[t];
+    }
+  };
+  f4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+  const int nchunks = ke > kb ? (int)((ke - kb + kGK - 1) / kGK) : 0;
+  if (nchunks > 0) {
+    gload(kb);
+    sstore(0);
+  }
+  __syncthreads();
+  const int r16 = lane & 15, k4 = lane >> 4;
+  for (int ch = 0; ch < nchunks; ++ch) {
+    const int cur = ch & 1;
+    if (ch + 1 < nchunks) gload(kb + (int64_t)(ch + 1) * kGK);
+#pragma unroll
+    for (int ks = 0; ks < kGK; ks += 4) {
+      float a[2], b[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) a[t] = As[cur][as_pos(ks + k4, wr + 16 * t + r16)];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) b[t] = Bs[cur][bs_pos(ks + k4, wc + 16 * t + r16)];
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[x], b[y], acc[x][y], 0, 0, 0);
+    }
+    if (ch + 1 < nchunks) sstore(cur ^ 1);
+    __syncthreads();
+  }
+  float* C = (float*)g.C;
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t i = i0 + wr + 16 * x + 4 * k4 + r, j = j0 + wc + 16 * y + r16;
+        if (i < g.M && j < g.N) C[i + j * g.ldc] = (float)g.alpha * acc[x][y][r];
+      }
 }
 
 size_t gemm_workspace_bytes(int64_t M, int64_t N, int splits) {
@@ -192,9 +288,10 @@ int gemm_pick_splits(int64_t M, int64_t N, int64_t K, int num_cus) {
   return s < 1 ? 1 : (int)s;
 }
 
-hipError_t launch_gemm(int transA, int transB, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
-                       int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int flags,
-                       int splits, double* work, const int32_t* info, hipStream_t s) {
+static hipError_t launch_gemm_impl(int ta_f32, int tb_f32, int transA, int transB, int64_t M, int64_t N, int64_t K,
+                                   double alpha, const void* A, int64_t lda, const void* B, int64_t ldb, double beta,
+                                   double* C, int64_t ldc, int flags, int splits, double* work, const int32_t* info,
+                                   hipStream_t s) {
   if (M <= 0 || N <= 0) return hipSuccess;
   GemmArgs g{};
   g.M = M; g.N = N; g.K = K;
@@ -213,11 +310,47 @@ hipError_t launch_gemm(int transA, int transB, int64_t M, int64_t N, int64_t K, 
   g.ldp = M;
   if (splits > 1 && work == nullptr) return hipErrorInvalidValue;
   dim3 grid((unsigned)((M + kGM - 1) / kGM), (unsigned)((N + kGN - 1) / kGN), (unsigned)splits);
-  hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, s, g);
+  if (!ta_f32 && !tb_f32) hipLaunchKernelGGL((k_gemm<double, double>), grid, dim3(256), 0, s, g);
+  else if (ta_f32 && tb_f32) hipLaunchKernelGGL((k_gemm<float, float>), grid, dim3(256), 0, s, g);
+  else if (ta_f32) hipLaunchKernelGGL((k_gemm<float, double>), grid, dim3(256), 0, s, g);
+  else hipLaunchKernelGGL((k_gemm<double, float>), grid, dim3(256), 0, s, g);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || splits == 1) return e;
   const int64_t total = M * N;
   hipLaunchKernelGGL(k_gemm_reduce, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm(int transA, int transB, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
+                       int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int flags,
+                       int splits, double* work, const int32_t* info, hipStream_t s) {
+  return launch_gemm_impl(0, 0, transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, flags, splits, work,
+                          info, s);
+}
+
+hipError_t launch_gemm_in32(int a_f32, int b_f32, int transA, int transB, int64_t M, int64_t N, int64_t K,
+                            double alpha, const void* A, int64_t lda, const void* B, int64_t ldb, double beta,
+                            double* C, int64_t ldc, int flags, int splits, double* work, const int32_t* info,
+                            hipStream_t s) {
+  return launch_gemm_impl(a_f32, b_f32, transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, flags, splits,
+                          work, info, s);
+}
+
+hipError_t launch_gemm_f32(int transA, int transB, int64_t M, int64_t N, int64_t K, const double* A, int64_t lda,
+                           const double* B, int64_t ldb, float* C, int64_t ldc, int flags, const int32_t* info,
+                           hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  GemmArgs g{};
+  g.M = M; g.N = N; g.K = K;
+  g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc;
+  g.alpha = 1.0; g.beta = 0.0;
+  g.transA = transA; g.transB = transB; g.flags = flags & (GEMM_A_LOWER | GEMM_A_UPPER | GEMM_B_LOWER | GEMM_B_UPPER);
+  g.info = info;
+  g.splits = 1;
+  g.kchunk = (K + kGK - 1) / kGK * kGK;
+  if (g.kchunk < kGK) g.kchunk = kGK;
+  dim3 grid((unsigned)((M + kGM - 1) / kGM), (unsigned)((N + kGN - 1) / kGN), 1);
+  hipLaunchKernelGGL(k_gemm_f32, grid, dim3(256), 0, s, g);
   return hipGetLastError();
 }
 

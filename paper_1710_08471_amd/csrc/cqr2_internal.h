@@ -76,6 +76,16 @@ hipError_t launch_gemm(int transA, int transB, int64_t M, int64_t N, int64_t K, 
                        int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc, int flags,
                        int splits, double* work, const int32_t* info, hipStream_t s);
 
+// Same with FP32 inputs (exactly widened to FP64; a_f32 / b_f32 select float).
+hipError_t launch_gemm_in32(int a_f32, int b_f32, int transA, int transB, int64_t M, int64_t N, int64_t K,
+                            double alpha, const void* A, int64_t lda, const void* B, int64_t ldb, double beta,
+                            double* C, int64_t ldc, int flags, int splits, double* work, const int32_t* info,
+                            hipStream_t s);
+// C(float) = op(fl32(A)) op(fl32(B)) with FP32 products and sums (no split).
+hipError_t launch_gemm_f32(int transA, int transB, int64_t M, int64_t N, int64_t K, const double* A, int64_t lda,
+                           const double* B, int64_t ldb, float* C, int64_t ldc, int flags, const int32_t* info,
+                           hipStream_t s);
+
 // ---- recursive CholInv and the n > 128 driver --------------------------------
 int64_t cholinv_split(int64_t n);
 size_t cholinv_rec_workspace(int64_t n);
@@ -95,9 +105,11 @@ struct GeneralPlan {
          off_q1 = 0;
   size_t total = 0;
 };
-GeneralPlan plan_general(int64_t m, int64_t n);
+// mixed: pass 1's Q1 = A R1^-1 is formed with FP32 products and sums and kept
+// as an FP32 m x n block in the workspace (everything else stays FP64).
+GeneralPlan plan_general(int64_t m, int64_t n, bool mixed);
 hipError_t factor_general(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, int64_t ldq, double* R,
-                          int64_t ldr, char* ws, const GeneralPlan& p, int32_t* d_info, hipStream_t s,
+                          int64_t ldr, char* ws, const GeneralPlan& p, bool mixed, int32_t* d_info, hipStream_t s,
                           const TimerHook& th);
 
 // ---- small helpers ---------------------------------------------------------

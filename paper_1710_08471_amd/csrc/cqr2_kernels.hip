@@ -324,15 +324,15 @@ hipError_t launch_gram_reduce(const GramPlan& p, const double* partials, int n, 
 // the owners of column j publish it to a double-buffered LDS vector, every
 // thread forms L(:,j) and Y(j,:) from it and applies the rank-1 updates.
 // ============================================================================
-template <int T>
-__global__ __launch_bounds__(256) void k_cholinv(const double* __restrict__ W, int64_t ldw, int n,
+template <int T, int G>
+__global__ __launch_bounds__(G * G) void k_cholinv(const double* __restrict__ W, int64_t ldw, int n,
                                                  double* __restrict__ R, int64_t ldr, double* __restrict__ Rinv,
                                                  int64_t ldri, double* __restrict__ Upad, int np,
                                                  int32_t* __restrict__ info, int info_offset) {
-  constexpr int NP = 16 * T;
+  constexpr int NP = G * T;
   __shared__ double colbuf[2][NP];
   const int tid = threadIdx.x;
-  const int r = tid >> 4, c = tid & 15;
+  const int r = tid / G, c = tid % G;
   int fail = 0;
   if (info != nullptr && *info != 0) fail = -1;  // an earlier phase failed: skip, NaN outputs
 
@@ -341,7 +341,7 @@ __global__ __launch_bounds__(256) void k_cholinv(const double* __restrict__ W, i
   for (int a = 0; a < T; ++a)
 #pragma unroll
     for (int b = 0; b < T; ++b) {
-      const int p = r + 16 * a, q = c + 16 * b;
+      const int p = r + G * a, q = c + G * b;
       double v = 0.0;
       if (p >= q) v = (p < n) ? W[p + (int64_t)q * ldw] : (p == q ? 1.0 : 0.0);
       M[a][b] = v;
@@ -350,9 +350,9 @@ __global__ __launch_bounds__(256) void k_cholinv(const double* __restrict__ W, i
   if (fail == 0) {
 #pragma unroll
     for (int jb = 0; jb < T; ++jb) {
-      if (16 * jb >= n || fail != 0) break;
-      for (int jc = 0; jc < 16; ++jc) {
-        const int j = 16 * jb + jc;
+      if (G * jb >= n || fail != 0) break;
+      for (int jc = 0; jc < G; ++jc) {
+        const int j = G * jb + jc;
         if (j >= n) break;
         double* buf = colbuf[j & 1];
         if (c == jc) {
@@ -370,20 +370,20 @@ __global__ __launch_bounds__(256) void k_cholinv(const double* __restrict__ W, i
         double lvp[T], yvp[T], lvq[T];
 #pragma unroll
         for (int a = 0; a < T; ++a) {
-          const int p = r + 16 * a;
+          const int p = r + G * a;
           const double v = buf[r * T + a];
           lvp[a] = (p > j) ? v * y : 0.0;
           yvp[a] = (p < j) ? v * y : (p == j ? y : 0.0);
         }
 #pragma unroll
         for (int b = 0; b < T; ++b) {
-          const int q = c + 16 * b;
+          const int q = c + G * b;
           lvq[b] = (q > j) ? buf[c * T + b] * y : 0.0;
         }
         if (c == jc) {
 #pragma unroll
           for (int a = 0; a < T; ++a) {
-            const int p = r + 16 * a;
+            const int p = r + G * a;
             M[a][jb] = (p > j) ? lvp[a] : (p == j ? sd : yvp[a]);
           }
         }
@@ -412,7 +412,7 @@ __global__ __launch_bounds__(256) void k_cholinv(const double* __restrict__ W, i
   for (int a = 0; a < T; ++a)
 #pragma unroll
     for (int b = 0; b < T; ++b) {
-      const int p = r + 16 * a, q = c + 16 * b;
+      const int p = r + G * a, q = c + G * b;
       const double v = M[a][b];
       if (p < n && q < n) {
         if (p >= q) {
@@ -443,14 +443,30 @@ int padded_order(int64_t n) {
   return 128;
 }
 
+// Thread grid of the one-workgroup CholInv: G x G threads, each owning a
+// (n/G) x (n/G) cyclic tile.
+#ifndef CQR2_CHOLINV_G
+#define CQR2_CHOLINV_G 32
+#endif
+
 hipError_t launch_cholinv(const double* W, int64_t ldw, int n, double* R, int64_t ldr, double* Rinv,
                           int64_t ldri, double* Upad, int np, int32_t* info, int info_offset,
                           hipStream_t s) {
-  const int t = padded_order(n) / 16;
+  constexpr int G = CQR2_CHOLINV_G;
+  const int t = padded_order(n) / G;
   switch (t) {
-    case 2: hipLaunchKernelGGL(k_cholinv<2>, dim3(1), dim3(256), 0, s, W, ldw, n, R, ldr, Rinv, ldri, Upad, np, info, info_offset); break;
-    case 4: hipLaunchKernelGGL(k_cholinv<4>, dim3(1), dim3(256), 0, s, W, ldw, n, R, ldr, Rinv, ldri, Upad, np, info, info_offset); break;
-    case 8: hipLaunchKernelGGL(k_cholinv<8>, dim3(1), dim3(256), 0, s, W, ldw, n, R, ldr, Rinv, ldri, Upad, np, info, info_offset); break;
+#define CQR2_CI(TV)                                                                                           \
+  case TV:                                                                                                    \
+    hipLaunchKernelGGL((k_cholinv<TV, G>), dim3(1), dim3(G * G), 0, s, W, ldw, n, R, ldr, Rinv, ldri, Upad, np, \
+                       info, info_offset);                                                                    \
+    break;
+    CQR2_CI(1)
+    CQR2_CI(2)
+    CQR2_CI(4)
+#if CQR2_CHOLINV_G == 16
+    CQR2_CI(8)
+#endif
+#undef CQR2_CI
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -1,0 +1,117 @@
+"""CholeskyQR2 with CQR2_MIXED_P1_FP32: pass 1's Q1 = A R1^-1 in FP32
+arithmetic (FP32 products and sums, FP32 Q1), Gram, CholInv and pass 2 in FP64.
+
+The paper fixes no precision, so this form has no printed result to match.
+It is held to: the orthogonality gate ||QᵀQ - I||_F <= 1e-12 (pass 2 restores
+it); the residual and R at the FP32 rounding level against the FP64 oracle,
+bounded per condition number; the oracle's own mixed form at the same level
+(FP32 sums in a different order); and bitwise equality with the FP64 result
+on inputs for which every FP32 operation of pass 1 is exact.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from synth import gdv_matrix
+from synth.matrices import MIXED_KAPPAS
+from tests.gpu_util import to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+MIXED = 1              # CQR2_MIXED_P1_FP32
+TOL_ORTH = 1e-12
+U32 = 2.0 ** -24
+TOL_RES = 200 * U32     # ||A - QR|| / ||A||: fl32(A) alone is a u32-level backward error
+TOL_R = 200 * U32       # ||R - R_fp64|| / ||R_fp64||
+
+
+def mixed_factor(lib, a):
+    import torch
+    info = torch.full((1,), -7, dtype=torch.int32, device="cuda")
+    q, r = lib.factor_ex(to_dev(a), info=info, flags=MIXED)
+    return to_host(q), to_host(r), int(info.item())
+
+
+@pytest.mark.parametrize("m,n,kappa,seed", [
+    (4096, 64, 1e3, 51), (20000, 33, 1e6, 52), (262144 // 8, 256, 1e2, 53), (262144 // 8, 256, 1e4, 54),
+    (262144 // 8, 256, 1e6, 55), (262144 // 8, 256, 1e7, 56), (3001, 300, 1e5, 57), (1000, 17, 1e3, 58),
+])
+def test_mixed_gates_against_fp64_oracle(gpu_lib, m, n, kappa, seed):
+    a = gdv_matrix(m, n, kappa, seed)
+    q, r, info = mixed_factor(gpu_lib, a)
+    assert info == 0
+    assert np.array_equal(r, np.triu(r)) and np.all(np.diag(r) > 0)
+    assert oracle.orthogonality(q) <= TOL_ORTH
+    assert oracle.residual(a, q, r) <= TOL_RES
+    q_ref, r_ref = oracle.cqr2(a)
+    assert oracle.rel_fro(r, r_ref) <= TOL_R
+    # against the oracle's mixed form: same precision, other FP32 summation order.
+    # Q is conditioned like A (an FP32-level change of R moves Q by ~kappa u32),
+    # so Q is compared only where that is small.
+    qm, rm = oracle.cqr2_mixed(a)
+    assert oracle.rel_fro(r, rm) <= TOL_R
+    if kappa <= 1e4:
+        assert oracle.rel_fro(q, qm) <= max(TOL_R, 50 * U32 * kappa)
+
+
+def hadamard_times_bidiagonal(m, n, seed):
+    """A = H R with H orthogonal ±1 columns (norm sqrt(m), m a power of 4) and R
+    bidiagonal with power-of-two diagonal and ±1 superdiagonal: R^-1 has dyadic
+    entries, every FP32 product and partial sum of Q1 = A R1^-1 is exact, and the
+    factors are exactly Q = H / sqrt(m), R = sqrt(m) R."""
+    rng = np.random.default_rng(seed)
+    k = 1
+    while k < max(n + 1, 2):
+        k *= 2
+    h = np.array([[1.0]])
+    while h.shape[0] < k:
+        h = np.block([[h, h], [h, -h]])
+    hcols = np.vstack([h] * (m // k))[:, 1:n + 1]
+    d = 2.0 ** rng.integers(-1, 2, n)
+    r = np.diag(d) @ (np.eye(n) + np.diag(rng.choice([-1.0, 1.0], n - 1), 1))
+    return hcols, r, hcols @ r
+
+
+@pytest.mark.parametrize("m,n", [(4096, 48), (4096, 200), (16384, 130)])
+def test_mixed_exact_case_bitwise(gpu_lib, m, n):
+    hcols, rr, a = hadamard_times_bidiagonal(m, n, 60 + n)
+    q, r, info = mixed_factor(gpu_lib, a)
+    assert info == 0
+    s = np.sqrt(m)
+    assert np.array_equal(r, s * rr)
+    assert np.array_equal(q, hcols / s)
+    qf, rf = gpu_lib.factor(to_dev(a))
+    assert np.array_equal(to_host(qf), q) and np.array_equal(to_host(rf), r)
+
+
+def test_mixed_breakdown_and_determinism(gpu_lib):
+    a = gdv_matrix(6000, 40, 10.0, 61)
+    q1, r1, i1 = mixed_factor(gpu_lib, a)
+    q2, r2, i2 = mixed_factor(gpu_lib, a)
+    assert i1 == i2 == 0
+    assert np.array_equal(q1, q2) and np.array_equal(r1, r2)
+    a[:, 7] = 0.0
+    q, r, info = mixed_factor(gpu_lib, a)
+    assert info == 8
+    assert np.all(np.isnan(r))
+
+
+def test_mixed_workspace_holds_fp32_q1(gpu_lib):
+    m, n = 262144, 256
+    w64 = gpu_lib.workspace_size(m, n, 0)
+    w32 = gpu_lib.workspace_size(m, n, MIXED)
+    assert w32 > 0 and w64 - w32 >= m * n * 4 - 4096
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("kappa", sorted(MIXED_KAPPAS))
+def test_mixed_full_size_kappa_sweep(gpu_lib, kappa):
+    """The 262144 x 256 comparison problem at each condition number of the sweep."""
+    from synth import workload_matrix
+    a = workload_matrix("mixed_262144x256", kappa)
+    q, r, info = mixed_factor(gpu_lib, a)
+    assert info == 0
+    assert oracle.orthogonality(q) <= TOL_ORTH
+    assert oracle.residual(a, q, r) <= TOL_RES
+    q_ref, r_ref = oracle.cqr2(a)
+    assert oracle.rel_fro(r, r_ref) <= TOL_R
