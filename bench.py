@@ -3,11 +3,13 @@
 One step = one full CholeskyQR2 (both passes and R = R2 R1) through the C ABI
 (cqr2_factor) on a device-resident synthetic matrix A = G diag(logspace(0,-6,128)) V.
 Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+--workload / --mixed time the other named problems (cqr2_factor_ex with the
+given flags) with the same JSON layout; the default is the 1048576 x 128 one.
 """
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -20,7 +22,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP64_PEAK_TFLOPS = 78.6        # MI355X dense FP64 (vector and matrix)
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1710_08471_amd", "csrc", "cqr2_kernels.hip")
+METRIC = "CQR2 GFLOP/s + HBM roofline % (1M\u00d7128 FP64); served solves/s, p99 latency"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_tall_1Mx128.json")
 
 
@@ -38,40 +40,52 @@ def flops_householder(m: int, n: int) -> float:
     return 2.0 * m * n * n - 2.0 * n ** 3 / 3.0
 
 
-def kernel_units(name: str, m: int, n: int):
-    """Algorithmic work of one launch: (bound, flops, bytes)."""
-    tri = m * n * (n + 1)            # 2 flops per multiply-add over the lower / upper triangle
-    if name == "gram":
+# Timer classes of the library (cqr2_timing_read order) grouped by the kernel
+# they time on the n <= 128 FP64 path.
+KERNEL_CLASSES = {
+    "k_apply_rinv": ("apply_rinv_pass1", "apply_rinv_pass2"),
+    "k_gram_partials": ("gram",),
+    "k_gram_reduce": ("gram_reduce",),
+    "k_cholinv": ("cholinv",),
+    "k_gemm+k_finalize_r": ("upper_product",),
+}
+
+
+def kernel_units(kernel: str, m: int, n: int, mixed: bool = False):
+    """Algorithmic work of ONE launch of `kernel` at (m, n): (bound, flops, bytes).
+
+    Flops count multiply-adds of the triangle actually needed (2 per product);
+    bytes are the minimum HBM traffic: each operand read once, each output
+    written once.
+    """
+    tri = m * n * (n + 1)            # 2 flops x (n (n+1) / 2 products per row)
+    if kernel == "k_gram_partials":
         return "mfma", float(tri), 8.0 * m * n                  # reads A once
-    if name in ("apply_rinv_pass1", "apply_rinv_pass2"):
+    if kernel == "k_apply_rinv":
         return "hbm", float(tri), 16.0 * m * n                  # reads A, writes Q
-    if name == "gram_reduce":
+    if kernel == "k_gram_reduce":
         ng = 1
         while ng < (n + 3) // 4:
             ng *= 2
         return "hbm", 0.0, 8.0 * 256 * 16 * (ng * (ng + 1) // 2)  # partial Grams read once
-    if name == "cholinv":
+    if kernel == "k_cholinv":
         return "alu", 2.0 * n ** 3 / 3.0, 8.0 * n * n
     return "alu", 2.0 * n ** 3 / 3.0, 24.0 * n * n
-
-
-def source_sha() -> str:
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
 def read_traffic(kernel: str):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they
     were taken on the current kernel source; else None."""
+    from paper_1710_08471_amd.profiling import source_sha
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("source_sha") != source_sha():
-        return None
     k = t.get("kernels", {}).get(kernel)
-    return None if k is None else float(k["bytes_per_launch"])
+    if k is None or k.get("source_sha") != source_sha(kernel):
+        return None
+    return float(k["bytes_per_launch"])
 
 
 def cpu_baseline(a, budget_s: float):
@@ -88,7 +102,7 @@ def cpu_baseline(a, budget_s: float):
         t0 = time.perf_counter()
         oracle.cqr2(a)
         times.append(time.perf_counter() - t0)
-        if time.perf_counter() - t_start + times[-1] > budget_s or len(times) >= 5:
+        if time.perf_counter() - t_start + times[-1] > budget_s or len(times) >= 25:
             break
     cores = os.cpu_count()
     if threadpool_info is not None:
@@ -101,7 +115,8 @@ def cpu_baseline(a, budget_s: float):
         "unit": "GFLOP/s",
         "cores": cores,
         "kind": "oracle",
-        "sample": f"full {m}x{n} matrix, median of {len(times)} oracle CholeskyQR2 runs ({t:.3f} s each)",
+        "sample": f"the full {m}x{n} matrix, median of {len(times)} oracle CholeskyQR2 runs "
+                  f"({t:.3f} s each, {sum(times):.1f} s of CPU work)",
     }
 
 
@@ -110,6 +125,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="tall_1Mx128",
+                    help="tall_1Mx128 (default), tall_4096x64, rect_65536x4096 or mixed_262144x256")
+    ap.add_argument("--kappa", type=float, default=None, help="condition number (mixed_262144x256 sweep)")
+    ap.add_argument("--mixed", action="store_true", help="CQR2_MIXED_P1_FP32 (pass-1 Q1 in FP32)")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
@@ -120,32 +139,41 @@ def main():
               "(run with --gpus 1).", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_1710_08471_amd as cq
     from synth import WORKLOADS, workload_matrix
 
-    wl = WORKLOADS["tall_1Mx128"]
+    wl = WORKLOADS[args.workload]
     m, n = wl.m, wl.n
+    flags = cq.CQR2_MIXED_P1_FP32 if args.mixed else cq.CQR2_FP64
+    default_run = args.workload == "tall_1Mx128" and not args.mixed
     log(f"generating {wl.description} (seed {wl.seed}) on the host ...")
     t0 = time.perf_counter()
-    a_host = workload_matrix("tall_1Mx128")
+    a_host = workload_matrix(args.workload, args.kappa)
     log(f"  generated in {time.perf_counter() - t0:.1f} s")
 
-    cq.load()
+    lib = cq.load()
     dev = torch.device("cuda:0")
     a = cq.colmajor(torch.from_numpy(a_host).to(dev))
     q = cq.empty_colmajor(m, n, device=dev)
     r = cq.empty_colmajor(n, n, device=dev)
-    lib = cq.load()
     stream = torch.cuda.current_stream()
     sp = cq.ctypes.c_void_p(stream.cuda_stream)
+    if default_run:
+        def step():
+            rc = lib.cqr2_factor(cq._ptr(a), m, n, m, cq._ptr(q), cq._ptr(r), sp)
+            if rc != 0:
+                raise cq.CQR2Error(rc, "cqr2_factor")
+    else:
+        wbytes = lib.cqr2_workspace_size(m, n, flags)
+        work = torch.empty(max(wbytes, 256), dtype=torch.uint8, device=dev)
 
-    def step():
-        rc = lib.cqr2_factor(cq._ptr(a), m, n, m, cq._ptr(q), cq._ptr(r), sp)
-        if rc != 0:
-            raise cq.CQR2Error(rc, "cqr2_factor")
+        def step():
+            rc = lib.cqr2_factor_ex(cq._ptr(a), m, n, m, cq._ptr(q), m, cq._ptr(r), n, cq._ptr(work), wbytes,
+                                    None, flags, sp)
+            if rc != 0:
+                raise cq.CQR2Error(rc, "cqr2_factor_ex")
 
     for _ in range(args.warmup):
         step()
@@ -162,7 +190,8 @@ def main():
     ms_per_step = elapsed * 1e3 / args.steps
     log(f"timed {args.steps} steps: {ms_per_step:.4f} ms/step")
 
-    # Same K steps again with HIP events around every kernel (on this stream).
+    # The same K steps again with a HIP event pair around every kernel, recorded
+    # by the library on the stream the kernels run on.
     cq.timing_reset()
     cq.timing_enable(True)
     torch.cuda.synchronize()
@@ -173,7 +202,7 @@ def main():
     inst_ms = (time.perf_counter() - t1) * 1e3 / args.steps
     cq.timing_enable(False)
     kt = cq.timing_read()
-    log("per-kernel (HIP events): " + ", ".join(
+    log("per-class (HIP events): " + ", ".join(
         f"{k} {v[0] / max(v[1], 1) * 1e3:.1f} us x{v[1] // args.steps}" for k, v in kt.items() if v[1]))
 
     if args.calib_copy_gib > 0:
@@ -194,28 +223,8 @@ def main():
     value = flops_cqr2(m, n) / t_step / 1e9
     hbm_bytes_6mn = 6.0 * m * n * 8
 
-    # Dominant kernel and its roofline.
-    per_kernel = {k: (v[0] / v[1], v[1]) for k, v in kt.items() if v[1]}
-    totals = {k: v[0] for k, v in kt.items() if v[1]}
-    dom_cls = max(totals, key=totals.get)
-    dom_avg_ms = per_kernel[dom_cls][0]
-    bound, fl, by = kernel_units(dom_cls, m, n)
-    kname = {"gram": "k_gram_partials", "apply_rinv_pass1": "k_apply_rinv", "apply_rinv_pass2": "k_apply_rinv",
-             "gram_reduce": "k_gram_reduce", "cholinv": "k_cholinv", "upper_product": "k_upper_product"}[dom_cls]
-    if bound == "hbm":
-        achieved = by / (dom_avg_ms / 1e3) / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4)}
-    else:
-        achieved = fl / (dom_avg_ms / 1e3) / 1e12
-        roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP64_PEAK_TFLOPS, 4)}
-    roof["kernel"] = f"{kname} ({dom_cls})"
-    roof["avg_launch_ms"] = round(dom_avg_ms, 5)
-    roof["traffic"] = read_traffic(dom_cls)
-
     out = {
-        "metric": "CQR2 GFLOP/s (1M x 128 FP64)",
+        "metric": METRIC if default_run else f"CQR2 GFLOP/s ({args.workload}{' mixed' if args.mixed else ''})",
         "value": round(value, 2),
         "unit": "GFLOP/s",
         "n_gpus": 1,
@@ -225,19 +234,42 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64+f32" if args.mixed else "f64",
         "data": "synthetic",
-        "config": {"workload": "tall_1Mx128", "m": m, "n": n, "lda": m, "kappa": wl.kappa, "seed": wl.seed,
-                   "matrix": "A = G diag(logspace(0,-6,128)) V, G orthonormal 1048576x128, V orthogonal"},
-        "hbm_roofline_frac_6mn": round(hbm_bytes_6mn / t_step / 1e9 / HBM_PEAK_GBS, 4),
+        "config": {"workload": args.workload, "m": m, "n": n, "lda": m,
+                   "kappa": args.kappa if args.kappa is not None else wl.kappa, "seed": wl.seed,
+                   "flags": "CQR2_MIXED_P1_FP32" if args.mixed else "CQR2_FP64", "matrix": wl.description},
+        "hbm_roofline_pct_6mn": round(100.0 * hbm_bytes_6mn / t_step / 1e9 / HBM_PEAK_GBS, 2),
         "paper_convention_gflops": round(flops_householder(m, n) / t_step / 1e9, 2),
-        "kernel_ms": {k: round(v[0], 5) for k, v in per_kernel.items()},
+        "class_ms": {k: round(v[0] / v[1], 5) for k, v in kt.items() if v[1]},
         "instrumented_ms_per_step": round(inst_ms, 5),
         "orthogonality": orth,
         "residual": resid,
-        "roofline": roof,
     }
-    if not args.no_cpu_baseline:
+
+    # Dominant kernel (largest total time over the K instrumented steps) and its
+    # roofline; only the n <= 128 FP64 path has one kernel per timer class.
+    if n <= 128 and not args.mixed:
+        tot = {k: sum(kt[c][0] for c in cls if kt.get(c, (0, 0))[1]) for k, cls in KERNEL_CLASSES.items()}
+        cnt = {k: sum(kt[c][1] for c in cls if kt.get(c, (0, 0))[1]) for k, cls in KERNEL_CLASSES.items()}
+        dom = max(tot, key=tot.get)
+        avg_ms = tot[dom] / cnt[dom]
+        bound, fl, by = kernel_units(dom, m, n)
+        if bound == "hbm":
+            achieved = by / (avg_ms / 1e3) / 1e9
+            roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4)}
+        else:
+            achieved = fl / (avg_ms / 1e3) / 1e12
+            roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(achieved / FP64_PEAK_TFLOPS, 4)}
+        roof["traffic"] = read_traffic(dom) if default_run else None
+        roof["kernel"] = dom
+        roof["launches_per_step"] = cnt[dom] // args.steps
+        roof["avg_launch_ms"] = round(avg_ms, 5)
+        roof["algorithmic_per_launch"] = by if bound == "hbm" else fl
+        out["roofline"] = roof
+    if default_run and not args.no_cpu_baseline:
         log("timing the CPU oracle ...")
         out["cpu_baseline"] = cpu_baseline(a_host, args.cpu_budget)
     print(json.dumps(out), flush=True)

@@ -93,6 +93,15 @@ hipError_t cholinv_recursive(double* W, int64_t ldw, int64_t n, double* R, int64
   return hipSuccess;
 }
 
+__global__ void k_set_info(int32_t* info, int32_t value) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *info = value;
+}
+
+hipError_t launch_set_info(int32_t* info, int32_t value, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_info, dim3(1), dim3(64), 0, s, info, value);
+  return hipGetLastError();
+}
+
 // W(j, i) = W(i, j) for i > j (complete a lower-triangle result).
 __global__ void k_mirror_lower(double* W, int64_t ldw, int64_t n) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

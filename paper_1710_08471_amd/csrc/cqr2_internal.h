@@ -1,5 +1,6 @@
 // Internal launch interface between the C ABI (cqr2_api.hip) and the kernels
-// (cqr2_kernels.hip).  Not installed; no torch types anywhere.
+// (cqr2_gram.hip, cqr2_cholinv.hip, cqr2_apply.hip, cqr2_gemm.hip, cqr2_driver.hip).
+// Not installed; no torch types anywhere.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <cstddef>

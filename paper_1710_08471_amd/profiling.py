@@ -1,0 +1,186 @@
+"""Summaries of rocprofv3 output for the committed profile records.
+
+Two reports, each written as short text (plus JSON for traffic) that names the
+command which produced the raw data:
+
+  stats   -- from ``rocprofv3 --kernel-trace --stats --output-format csv``:
+             per kernel the number of dispatches and the average / total
+             duration.
+  traffic -- from two ``rocprofv3 --pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE``
+             runs of the same program: HBM bytes per dispatch of each kernel,
+             scaled by what the same counters read for a device copy of known
+             size in that program (the calibration).
+
+Usage:
+  python -m paper_1710_08471_amd.profiling stats DIR --command CMD --out FILE
+  python -m paper_1710_08471_amd.profiling traffic --fetch DIR --write DIR \\
+      --copy-bytes N --command-fetch CMD --command-write CMD --out-json F --out-txt F
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import glob
+import hashlib
+import json
+import os
+import re
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+
+# Source file that defines and launches each kernel family: a counter result
+# stays valid while that file is unchanged.
+KERNEL_SOURCE = {
+    "k_gram_partials": "cqr2_gram.hip",
+    "k_gram_reduce": "cqr2_gram.hip",
+    "k_cholinv": "cqr2_cholinv.hip",
+    "k_apply_rinv": "cqr2_apply.hip",
+    "k_gemm": "cqr2_gemm.hip",
+    "k_gemm_f32": "cqr2_gemm.hip",
+    "k_gemm_reduce": "cqr2_gemm.hip",
+}
+COPY_KERNEL = "__amd_rocclr_copyBuffer"
+
+
+def source_sha(kernel: str) -> str:
+    """Short hash of the source file of `kernel` (cqr2_driver.hip if unlisted)."""
+    path = os.path.join(PKG, "csrc", KERNEL_SOURCE.get(kernel, "cqr2_driver.hip"))
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def short_name(name: str) -> str:
+    """'void cqr2::k_apply_rinv<128, 2>(...)' -> 'k_apply_rinv<128, 2>'."""
+    base = name.split("(")[0] if not name.startswith("__") else name
+    base = re.sub(r"^void\s+", "", base)
+    base = base.replace("cqr2::", "")
+    return base.strip()[:90]
+
+
+def kernel_family(name: str) -> str:
+    """Template-free kernel name: 'k_apply_rinv<128, 2>' -> 'k_apply_rinv'."""
+    return short_name(name).split("<")[0]
+
+
+def _find(dirpath: str, suffix: str) -> str:
+    hits = sorted(glob.glob(os.path.join(dirpath, "**", "*" + suffix), recursive=True))
+    if not hits:
+        raise FileNotFoundError(f"no *{suffix} under {dirpath}")
+    return hits[0]
+
+
+def stats_report(dirpath: str, command: str) -> str:
+    path = _find(dirpath, "_kernel_stats.csv")
+    rows = list(csv.DictReader(open(path)))
+    lines = [
+        "rocprofv3 kernel statistics",
+        f"command: {command}",
+        "",
+        f"{'kernel':<60} {'calls':>6} {'avg_us':>10} {'min_us':>10} {'max_us':>10} {'total_ms':>10} {'pct':>6}",
+    ]
+    for r in rows:
+        calls = int(r["Calls"])
+        total = float(r["TotalDurationNs"])
+        avg = float(r["AverageNs"])
+        lines.append(f"{short_name(r['Name'])[:60]:<60} {calls:>6} {avg / 1e3:>10.2f} "
+                     f"{float(r['MinNs']) / 1e3:>10.2f} {float(r['MaxNs']) / 1e3:>10.2f} {total / 1e6:>10.3f} "
+                     f"{float(r['Percentage']):>6.2f}")
+    return "\n".join(lines) + "\n"
+
+
+def _counter_means(dirpath: str, counter: str):
+    """{kernel: (mean value per dispatch, dispatches)}; the copy kernel's entry
+    is the calibration copy alone: the last of its dispatches with the largest
+    grid (the program's other copies, e.g. host-to-device staging, differ)."""
+    path = _find(dirpath, "_counter_collection.csv")
+    vals = collections.defaultdict(list)
+    copies = []
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] != counter:
+            continue
+        name = short_name(r["Kernel_Name"])
+        if name == COPY_KERNEL:
+            copies.append((int(r["Grid_Size"]), int(r["Dispatch_Id"]), float(r["Counter_Value"])))
+        else:
+            vals[name].append(float(r["Counter_Value"]))
+    out = {k: (sum(v) / len(v), len(v)) for k, v in vals.items()}
+    if copies:
+        out[COPY_KERNEL] = (max(copies)[2], 1)
+    return out
+
+
+def traffic_report(fetch_dir: str, write_dir: str, copy_bytes: int, cmd_fetch: str, cmd_write: str):
+    fetch = _counter_means(fetch_dir, "FETCH_SIZE")
+    write = _counter_means(write_dir, "WRITE_SIZE")
+    copy_f = fetch.get(COPY_KERNEL)
+    copy_w = write.get(COPY_KERNEL)
+    if copy_f is None or copy_w is None:
+        raise RuntimeError("calibration copy kernel not found in the counter runs")
+    # counters are in KiB per dispatch; the copy reads and writes copy_bytes
+    f_scale = copy_bytes / (copy_f[0] * 1024.0)
+    w_scale = copy_bytes / (copy_w[0] * 1024.0)
+    kernels = {}
+    for name in sorted(set(fetch) & set(write)):
+        if not name.startswith("k_"):
+            continue
+        fam = kernel_family(name)
+        rd = fetch[name][0] * 1024.0 * f_scale
+        wr = write[name][0] * 1024.0 * w_scale
+        kernels[fam] = {"name": name, "dispatches": fetch[name][1], "read_bytes_per_launch": rd,
+                        "write_bytes_per_launch": wr, "bytes_per_launch": rd + wr,
+                        "source": KERNEL_SOURCE.get(fam, "cqr2_driver.hip"), "source_sha": source_sha(fam)}
+    data = {
+        "calibration": {"copy_bytes": copy_bytes, "fetch_kib": copy_f[0], "write_kib": copy_w[0],
+                        "fetch_scale": f_scale, "write_scale": w_scale},
+        "commands": {"fetch": cmd_fetch, "write": cmd_write},
+        "kernels": kernels,
+    }
+    lines = [
+        "HBM traffic per dispatch from rocprofv3 counters (FETCH_SIZE, WRITE_SIZE in KiB, scaled)",
+        f"command (FETCH_SIZE): {cmd_fetch}",
+        f"command (WRITE_SIZE): {cmd_write}",
+        f"calibration: device copy of {copy_bytes} B reads FETCH_SIZE {copy_f[0]:.1f} KiB, "
+        f"WRITE_SIZE {copy_w[0]:.1f} KiB -> scale read x{f_scale:.4f}, write x{w_scale:.4f}",
+        "",
+        f"{'kernel':<32} {'disp':>5} {'read_MB':>10} {'write_MB':>10} {'total_MB':>10}  source@sha",
+    ]
+    for fam, k in kernels.items():
+        lines.append(f"{k['name']:<32} {k['dispatches']:>5} {k['read_bytes_per_launch'] / 1e6:>10.2f} "
+                     f"{k['write_bytes_per_launch'] / 1e6:>10.2f} {k['bytes_per_launch'] / 1e6:>10.2f}  "
+                     f"{k['source']}@{k['source_sha']}")
+    return data, "\n".join(lines) + "\n"
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("dir")
+    s.add_argument("--command", required=True)
+    s.add_argument("--out", required=True)
+    t = sub.add_parser("traffic")
+    t.add_argument("--fetch", required=True)
+    t.add_argument("--write", required=True)
+    t.add_argument("--copy-bytes", type=int, required=True)
+    t.add_argument("--command-fetch", required=True)
+    t.add_argument("--command-write", required=True)
+    t.add_argument("--out-json", required=True)
+    t.add_argument("--out-txt", required=True)
+    a = ap.parse_args()
+    if a.cmd == "stats":
+        text = stats_report(a.dir, a.command)
+        with open(a.out, "w") as f:
+            f.write(text)
+        print(text)
+    else:
+        data, text = traffic_report(a.fetch, a.write, a.copy_bytes, a.command_fetch, a.command_write)
+        with open(a.out_json, "w") as f:
+            json.dump(data, f, indent=1)
+        with open(a.out_txt, "w") as f:
+            f.write(text)
+        print(text)
+
+
+if __name__ == "__main__":
+    main()
