@@ -136,6 +136,86 @@ int cqr2_apply_rinv(const double* A, int64_t m, int64_t n, int64_t lda,
 int cqr2_upper_product(const double* R2, const double* R1, double* R, int64_t n,
                        int64_t ld, void* stream);
 
+/* ---- many problems at once ------------------------------------------------
+ * One CholeskyQR2 problem (all pointers device, column-major FP64; same rules
+ * as cqr2_factor_ex: m >= n >= 0, lda, ldq >= m, ldr >= n, Q and R must not
+ * overlap A or each other).  d_info: optional device word receiving the
+ * breakdown code (0, j or n + j), may be NULL.
+ */
+typedef struct {
+  const double* A;
+  double* Q;
+  double* R;
+  int64_t m, n, lda, ldq, ldr;
+  int32_t* d_info;
+} cqr2_problem;
+
+/* 0 if *p is a valid problem, else the negative code cqr2_factor_ex would
+ * return for it (A=-1, m=-2, n=-3, lda=-4, Q=-5, ldq=-6, R=-7, ldr=-8,
+ * d_info=-11; CQR2_ERR_UNSUPPORTED for n > CQR2_MAX_N). */
+int cqr2_problem_check(const cqr2_problem* p);
+
+/* Bytes of device workspace cqr2_factor_batched needs (0 if any problem is
+ * invalid or flags != CQR2_FP64). */
+size_t cqr2_batched_workspace_size(const cqr2_problem* probs, int32_t count, uint32_t flags);
+
+/*
+ * cqr2_factor_batched — CholeskyQR2 (Algorithm 5, FP64) of `count` independent
+ * problems of any shapes, enqueued on `stream`.  probs: host array, read
+ * during the call only.  Problems with n <= 128 advance together: six launches
+ * of one multi-problem kernel, each moving every problem through one phase
+ * (Gram, CholInv, Q = A R^-1; twice; R = R2 R1 with the last).  Problems with
+ * n > 128 run the tiled path one after another on the same stream.  work:
+ * >= cqr2_batched_workspace_size bytes, 256-byte aligned, device.  The task
+ * tables are staged through library-owned pinned host memory (the call may
+ * wait for an earlier call's staging buffer to be consumed).  Results equal
+ * those of the same problem run alone through the batched path, bit for bit.
+ * Returns 0, -1 (a problem is invalid: see cqr2_problem_check), -2 (count),
+ * -3 (work), -4 (work_bytes), -5 (flags) or CQR2_ERR_*.
+ */
+int cqr2_factor_batched(const cqr2_problem* probs, int32_t count, void* work, size_t work_bytes,
+                        uint32_t flags, void* stream);
+
+/* ---- continuous-batching server ------------------------------------------
+ * A host-side scheduler over the multi-problem kernel for a stream of
+ * requests of uneven m and n.  Each cqr2_server_step admits queued requests
+ * (first come, first served) while an active slot is free, the workspace arena
+ * has room and the in-flight footprint (bytes of A, Q, R and workspace of
+ * every admitted, unfinished request) stays within the budget; then it
+ * launches ONE multi-problem kernel that advances every active n <= 128
+ * request by one phase, so requests admitted at different times share each
+ * launch and a request finishes six steps after its admission.  Requests with
+ * n > 128 run the tiled path on a second stream of the server as soon as they
+ * are admitted, overlapping the steps.  Nothing blocks on the GPU except when
+ * the host runs more than a few steps ahead (pinned task-table ring).
+ * Completion times are HIP event times in milliseconds since the last
+ * cqr2_server_clock call.  A, Q and R stay owned by the caller and must stay
+ * valid until the request is reported done by cqr2_server_poll.
+ */
+typedef struct cqr2_server cqr2_server;
+
+/* arena_bytes: device workspace pool allocated now; footprint_budget: bytes
+ * (0 = no limit beyond the arena); max_active: slots (1..4096); stream: the
+ * stream steps run on.  Returns 0 and *out, or a negative argument index. */
+int cqr2_server_create(size_t arena_bytes, size_t footprint_budget, int32_t max_active, void* stream,
+                       cqr2_server** out);
+/* Waits for all work of the server, then frees it. */
+int cqr2_server_destroy(cqr2_server* s);
+/* Queue a request.  Returns 0, -1 (server), -2 (invalid problem), -3 (n == 0
+ * is rejected: nothing to do), or CQR2_ERR_TOO_LARGE if it could never be
+ * admitted (workspace above the arena or footprint above the budget). */
+int cqr2_server_submit(cqr2_server* s, const cqr2_problem* p, int64_t tag);
+/* Admit and launch one step.  n_active / n_queued (may be NULL): requests in
+ * flight and waiting after the step. */
+int cqr2_server_step(cqr2_server* s, int32_t* n_active, int32_t* n_queued);
+/* Finished requests (their GPU work has completed): up to max_count tags and
+ * completion times; *count receives the number written. */
+int cqr2_server_poll(cqr2_server* s, int64_t* tags, double* done_ms, int32_t max_count, int32_t* count);
+/* Records the reference event (time 0) on the server's stream and waits for it. */
+int cqr2_server_clock(cqr2_server* s);
+
+#define CQR2_ERR_TOO_LARGE (-102)
+
 /* Human-readable text for a return code. */
 const char* cqr2_status_string(int code);
 

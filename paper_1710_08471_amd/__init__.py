@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_PKG, "libcqr2.so")
 
 CQR2_ERR_HIP = -100
 CQR2_ERR_UNSUPPORTED = -101
+CQR2_ERR_TOO_LARGE = -102
 CQR2_FP64 = 0
 CQR2_MIXED_P1_FP32 = 1
 NUM_TIMERS = 6
@@ -39,7 +40,23 @@ SIGNATURES = {
     "cqr2_timing_enable": (_i32, [_i32]),
     "cqr2_timing_reset": (_i32, []),
     "cqr2_timing_read": (_i32, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), _i32]),
+    "cqr2_problem_check": (_i32, [_vp]),
+    "cqr2_batched_workspace_size": (_sz, [_vp, _i32, _u32]),
+    "cqr2_factor_batched": (_i32, [_vp, _i32, _vp, _sz, _u32, _vp]),
+    "cqr2_server_create": (_i32, [_sz, _sz, _i32, _vp, ctypes.POINTER(_vp)]),
+    "cqr2_server_destroy": (_i32, [_vp]),
+    "cqr2_server_submit": (_i32, [_vp, _vp, _i64]),
+    "cqr2_server_step": (_i32, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+    "cqr2_server_poll": (_i32, [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double), _i32,
+                                ctypes.POINTER(ctypes.c_int32)]),
+    "cqr2_server_clock": (_i32, [_vp]),
 }
+
+
+class Problem(ctypes.Structure):
+    """cqr2_problem: one CholeskyQR2 problem (device pointers, column-major)."""
+    _fields_ = [("A", _vp), ("Q", _vp), ("R", _vp), ("m", _i64), ("n", _i64), ("lda", _i64), ("ldq", _i64),
+                ("ldr", _i64), ("d_info", _vp)]
 
 _lib = None
 
@@ -230,3 +247,91 @@ def timing_read():
 
 def version() -> str:
     return load().cqr2_version().decode()
+
+
+def problem(A, Q, R, info=None) -> Problem:
+    """cqr2_problem for column-major device tensors A (m x n), Q (m x n), R (n x n)."""
+    m, n = A.shape
+    return Problem(A.data_ptr(), Q.data_ptr(), R.data_ptr(), m, n, _ld(A), _ld(Q), _ld(R),
+                   info.data_ptr() if info is not None else None)
+
+
+def factor_batched(As, infos=None):
+    """[(Q, R), ...] = CholeskyQR2 of every matrix in `As` (cqr2_factor_batched).
+
+    Problems with n <= 128 share six multi-problem launches; larger ones run
+    the tiled path in turn.  `infos`: optional int32 device tensor of len(As).
+    """
+    import torch
+    lib = load()
+    outs, probs = [], []
+    for i, A in enumerate(As):
+        _require_cuda_f64(A, "A")
+        m, n = A.shape
+        Q = empty_colmajor(m, n, device=A.device)
+        R = empty_colmajor(n, n, device=A.device)
+        outs.append((Q, R))
+        probs.append(problem(A, Q, R, infos[i:i + 1] if infos is not None else None))
+    arr = (Problem * len(probs))(*probs)
+    wb = lib.cqr2_batched_workspace_size(arr, len(probs), CQR2_FP64)
+    if wb == 0 and probs:
+        for i, p in enumerate(probs):
+            _check(lib.cqr2_problem_check(ctypes.byref(p)), f"problem {i}")
+    work = torch.empty(max(int(wb), 256), dtype=torch.uint8, device=As[0].device if As else "cuda")
+    _check(lib.cqr2_factor_batched(arr, len(probs), _ptr(work), work.numel(), CQR2_FP64, _stream()),
+           "cqr2_factor_batched")
+    return outs
+
+
+class Server:
+    """Continuous-batching CholeskyQR2 server (cqr2_server_*) on one stream.
+
+    submit() queues a problem with a tag; step() admits what fits and launches
+    one multi-problem step; poll() returns (tag, done_ms) of finished requests,
+    done_ms being GPU event time since the last clock() call.
+    """
+
+    def __init__(self, arena_bytes: int, footprint_budget: int = 0, max_active: int = 256, stream=None):
+        import torch
+        self._lib = load()
+        self._stream = stream or torch.cuda.current_stream()
+        h = _vp()
+        _check(self._lib.cqr2_server_create(arena_bytes, footprint_budget, max_active,
+                                            _vp(self._stream.cuda_stream), ctypes.byref(h)), "cqr2_server_create")
+        self._h = h
+        self._keep = {}
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            _check(self._lib.cqr2_server_destroy(self._h), "cqr2_server_destroy")
+        self._h = None
+        self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def clock(self):
+        _check(self._lib.cqr2_server_clock(self._h), "cqr2_server_clock")
+
+    def submit(self, tag: int, A, Q, R, info=None):
+        p = problem(A, Q, R, info)
+        _check(self._lib.cqr2_server_submit(self._h, ctypes.byref(p), tag), "cqr2_server_submit")
+        self._keep[tag] = (A, Q, R, info)   # tensors stay alive until done
+
+    def step(self):
+        act, q = ctypes.c_int32(), ctypes.c_int32()
+        _check(self._lib.cqr2_server_step(self._h, ctypes.byref(act), ctypes.byref(q)), "cqr2_server_step")
+        return act.value, q.value
+
+    def poll(self, max_count: int = 4096):
+        tags = (ctypes.c_int64 * max_count)()
+        ms = (ctypes.c_double * max_count)()
+        cnt = ctypes.c_int32()
+        _check(self._lib.cqr2_server_poll(self._h, tags, ms, max_count, ctypes.byref(cnt)), "cqr2_server_poll")
+        out = [(int(tags[i]), float(ms[i])) for i in range(cnt.value)]
+        for t, _ in out:
+            self._keep.pop(t, None)
+        return out

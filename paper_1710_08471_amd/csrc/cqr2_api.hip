@@ -218,6 +218,7 @@ const char* cqr2_status_string(int code) {
     case 0: return "success";
     case CQR2_ERR_HIP: return "HIP runtime error";
     case CQR2_ERR_UNSUPPORTED: return "unsupported problem size";
+    case CQR2_ERR_TOO_LARGE: return "request can never fit the server's arena or footprint budget";
     default: break;
   }
   if (code < 0 && code > -20) return "invalid argument (see the argument index = -code)";
@@ -256,6 +257,26 @@ int cqr2_factor_ex(const double* A, int64_t m, int64_t n, int64_t lda, double* Q
     return -9;
   if (d_info != nullptr && ((uintptr_t)d_info & 3u) != 0) return -11;
   return run_factor(A, m, n, lda, Q, ldq, R, ldr, (char*)work, d_info, flags, (hipStream_t)stream);
+}
+
+int cqr2_problem_check(const cqr2_problem* p) {
+  if (p == nullptr) return -1;
+  const int64_t m = p->m, n = p->n;
+  if (n < 0) return -3;
+  if (m < n) return -2;
+  if (p->lda < (m > 1 ? m : 1)) return -4;
+  if (p->ldq < (m > 1 ? m : 1)) return -6;
+  if (p->ldr < (n > 1 ? n : 1)) return -8;
+  if (p->d_info != nullptr && ((uintptr_t)p->d_info & 3u) != 0) return -11;
+  if (n == 0) return 0;
+  if (p->A == nullptr || !aligned8(p->A)) return -1;
+  if (p->Q == nullptr || !aligned8(p->Q)) return -5;
+  if (p->R == nullptr || !aligned8(p->R)) return -7;
+  if (n > CQR2_MAX_N) return CQR2_ERR_UNSUPPORTED;
+  const size_t ab = matrix_bytes(m, n, p->lda), qb = matrix_bytes(m, n, p->ldq), rb = matrix_bytes(n, n, p->ldr);
+  if (overlaps(p->A, ab, p->Q, qb)) return -5;
+  if (overlaps(p->A, ab, p->R, rb) || overlaps(p->Q, qb, p->R, rb)) return -7;
+  return 0;
 }
 
 int cqr2_factor(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, double* R, void* stream) {

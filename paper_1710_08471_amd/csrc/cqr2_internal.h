@@ -113,6 +113,36 @@ hipError_t factor_general(const double* A, int64_t m, int64_t n, int64_t lda, do
                           int64_t ldr, char* ws, const GeneralPlan& p, bool mixed, int32_t* d_info, hipStream_t s,
                           const TimerHook& th);
 
+// ---- multi-problem step (batched and serving paths, n <= 128) -------------
+// One launch advances every listed problem by one phase of CholeskyQR2:
+//   0 Gram(A) partials, 1 CholInv(sum of partials) -> R1, U1 = R1^-1,
+//   2 Q = A U1, 3 Gram(Q) partials, 4 CholInv -> R2, U2, 5 Q = Q U2 and R = R2 R1.
+// Workgroups are dealt to the problems by the table (task t owns workgroups
+// [wg0, wg0 + nwg)); tasks are sorted by wg0.
+constexpr int kStepThreads = 512;
+constexpr int kStepStages = 64;  // 64-row stages per Gram / Q workgroup (4096 rows)
+constexpr int kStepPhases = 6;
+struct StepTask {
+  const double* A;
+  int64_t lda;
+  double* Q;
+  int64_t ldq;
+  double* R;
+  int64_t ldr;
+  int32_t* user_info;  // optional; written in phase 5
+  char* ws;            // the problem's workspace (StepLayout)
+  int64_t m;
+  int32_t n, phase, wg0, nwg;
+};
+struct StepLayout {
+  int np = 0, ng = 0, nblk = 0, splits = 0;
+  size_t off_info = 0, off_part = 0, off_r1 = 0, off_r2 = 0, off_u1 = 0, off_u2 = 0, total = 0;
+};
+StepLayout step_layout(int64_t m, int64_t n);
+// Workgroups of phase `phase` for an m-row problem.
+int step_workgroups(int64_t m, int phase);
+hipError_t launch_step(const StepTask* d_tasks, int ntasks, int total_wgs, hipStream_t s);
+
 // ---- small helpers ---------------------------------------------------------
 hipError_t launch_set_info(int32_t* info, int32_t value, hipStream_t s);
 

@@ -1,0 +1,463 @@
+// Many CholeskyQR2 problems per launch: the batched entry point and the
+// continuous-batching server (host side).  Both drive the multi-problem step
+// kernel (cqr2_step.hip) for n <= 128 and the tiled path for larger n.
+//
+// Task tables travel host -> device through a ring of pinned host buffers;
+// a buffer is rewritten only after the copy that last read it has completed
+// (its event), which bounds how far the host runs ahead of the GPU.
+#include "cqr2.h"
+#include "cqr2_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <vector>
+
+namespace {
+
+constexpr int64_t kStepMaxN = 128;
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+size_t mat_bytes(int64_t rows, int64_t cols, int64_t ld) {
+  if (rows <= 0 || cols <= 0) return 0;
+  return (size_t)((cols - 1) * ld + rows) * sizeof(double);
+}
+
+size_t problem_workspace(const cqr2_problem& p) {
+  if (p.n <= 0) return 0;
+  if (p.n <= kStepMaxN) return align_up(cqr2::step_layout(p.m, p.n).total);
+  return align_up(cqr2::plan_general(p.m, p.n, false).total);
+}
+
+size_t problem_footprint(const cqr2_problem& p) {
+  return mat_bytes(p.m, p.n, p.lda) + mat_bytes(p.m, p.n, p.ldq) + mat_bytes(p.n, p.n, p.ldr) +
+         problem_workspace(p);
+}
+
+cqr2::StepTask make_task(const cqr2_problem& p, char* ws, int phase, int wg0) {
+  cqr2::StepTask t{};
+  t.A = p.A;
+  t.lda = p.lda;
+  t.Q = p.Q;
+  t.ldq = p.ldq;
+  t.R = p.R;
+  t.ldr = p.ldr;
+  t.user_info = p.d_info;
+  t.ws = ws;
+  t.m = p.m;
+  t.n = (int32_t)p.n;
+  t.phase = phase;
+  t.wg0 = wg0;
+  t.nwg = cqr2::step_workgroups(p.m, phase);
+  return t;
+}
+
+// Pinned host staging ring for task tables.
+class TableRing {
+ public:
+  explicit TableRing(int slots) : slots_(slots) {}
+  ~TableRing() { release(); }
+  void release() {
+    for (auto& s : ring_) {
+      if (s.ev) {
+        (void)hipEventSynchronize(s.ev);
+        (void)hipEventDestroy(s.ev);
+      }
+      if (s.host) (void)hipHostFree(s.host);
+    }
+    ring_.clear();
+  }
+  // Copies `bytes` from `src` to device `dst` on `s` through the next pinned
+  // buffer (waiting for that buffer's previous copy first).
+  hipError_t copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
+    if (ring_.empty()) ring_.resize(slots_);
+    Slot& sl = ring_[next_];
+    next_ = (next_ + 1) % slots_;
+    if (sl.ev) {
+      hipError_t e = hipEventSynchronize(sl.ev);
+      if (e != hipSuccess) return e;
+    } else {
+      hipError_t e = hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming);
+      if (e != hipSuccess) return e;
+    }
+    if (sl.cap < bytes) {
+      if (sl.host) (void)hipHostFree(sl.host);
+      sl.host = nullptr;
+      sl.cap = 0;
+      const size_t cap = std::max<size_t>(bytes, 64 * 1024);
+      hipError_t e = hipHostMalloc(&sl.host, cap, hipHostMallocDefault);
+      if (e != hipSuccess) return e;
+      sl.cap = cap;
+    }
+    std::memcpy(sl.host, src, bytes);
+    hipError_t e = hipMemcpyAsync(dst, sl.host, bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    return hipEventRecord(sl.ev, s);
+  }
+
+ private:
+  struct Slot {
+    void* host = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+  };
+  int slots_;
+  int next_ = 0;
+  std::vector<Slot> ring_;
+};
+
+std::mutex g_batched_mu;
+TableRing* g_batched_ring = nullptr;
+
+int to_code(hipError_t e) { return e == hipSuccess ? 0 : CQR2_ERR_HIP; }
+
+// First-fit allocator over [0, size) with coalescing frees (offsets 256-aligned).
+class Arena {
+ public:
+  void reset(size_t size) {
+    free_.clear();
+    if (size) free_[0] = size;
+    size_ = size;
+  }
+  bool alloc(size_t bytes, size_t* off) {
+    bytes = align_up(bytes ? bytes : kAlign);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        *off = it->first;
+        const size_t rest = it->second - bytes, noff = it->first + bytes;
+        free_.erase(it);
+        if (rest) free_[noff] = rest;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    bytes = align_up(bytes ? bytes : kAlign);
+    auto it = free_.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+  size_t size() const { return size_; }
+
+ private:
+  std::map<size_t, size_t> free_;
+  size_t size_ = 0;
+};
+
+}  // namespace
+
+// ---- continuous-batching server ---------------------------------------------
+struct cqr2_server {
+  struct Req {
+    cqr2_problem p;
+    int64_t tag;
+    size_t ws_bytes, footprint;
+    bool large;
+  };
+  struct Active {
+    Req r;
+    size_t ws_off;
+    int phase;
+  };
+  struct Finishing {
+    hipEvent_t ev;
+    std::vector<Req> reqs;
+    std::vector<size_t> offs;
+  };
+
+  hipStream_t stream = nullptr;       // steps
+  hipStream_t large_stream = nullptr; // n > 128 requests
+  char* arena_base = nullptr;
+  Arena arena;
+  size_t budget = 0, in_flight_bytes = 0;
+  int max_active = 0;
+  std::deque<Req> queue;
+  std::vector<Active> active;         // n <= 128, in phase order of admission
+  int n_large_running = 0;
+  std::deque<Finishing> finishing;
+  std::vector<std::pair<int64_t, double>> done;
+  std::vector<hipEvent_t> event_pool;
+  hipEvent_t t0 = nullptr;
+  TableRing ring{8};
+  std::vector<char*> dev_tables;      // one device table per ring slot
+  int dev_next = 0;
+  std::vector<cqr2::StepTask> table;
+
+  hipEvent_t get_event() {
+    if (!event_pool.empty()) {
+      hipEvent_t e = event_pool.back();
+      event_pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+
+  // Move finished work whose events have completed to `done`; free its memory.
+  // Entries complete out of order (two streams), so every entry is checked.
+  int reap() {
+    for (auto it = finishing.begin(); it != finishing.end();) {
+      const hipError_t q = hipEventQuery(it->ev);
+      if (q == hipErrorNotReady) {
+        ++it;
+        continue;
+      }
+      if (q != hipSuccess) return CQR2_ERR_HIP;
+      float ms = 0.f;
+      if (t0 != nullptr && hipEventElapsedTime(&ms, t0, it->ev) != hipSuccess) ms = -1.f;
+      for (size_t i = 0; i < it->reqs.size(); ++i) {
+        done.emplace_back(it->reqs[i].tag, (double)ms);
+        arena.release(it->offs[i], it->reqs[i].ws_bytes);
+        in_flight_bytes -= it->reqs[i].footprint;
+        if (it->reqs[i].large) --n_large_running;
+      }
+      event_pool.push_back(it->ev);
+      it = finishing.erase(it);
+    }
+    return 0;
+  }
+
+  int admit() {
+    while (!queue.empty() && (int)active.size() + n_large_running < max_active) {
+      Req& r = queue.front();
+      if (budget && in_flight_bytes + r.footprint > budget) break;
+      size_t off = 0;
+      if (!arena.alloc(r.ws_bytes, &off)) break;
+      in_flight_bytes += r.footprint;
+      if (!r.large) {
+        active.push_back({r, off, 0});
+      } else {
+        const cqr2_problem& p = r.p;
+        const cqr2::GeneralPlan plan = cqr2::plan_general(p.m, p.n, false);
+        hipError_t e = cqr2::factor_general(p.A, p.m, p.n, p.lda, p.Q, p.ldq, p.R, p.ldr, arena_base + off, plan,
+                                            false, p.d_info, large_stream, cqr2::TimerHook{});
+        if (e != hipSuccess) return CQR2_ERR_HIP;
+        hipEvent_t ev = get_event();
+        if (ev == nullptr || hipEventRecord(ev, large_stream) != hipSuccess) return CQR2_ERR_HIP;
+        ++n_large_running;
+        finishing.push_back({ev, {r}, {off}});
+      }
+      queue.pop_front();
+    }
+    return 0;
+  }
+
+  int step() {
+    int rc = reap();
+    if (rc) return rc;
+    rc = admit();
+    if (rc) return rc;
+    if (active.empty()) return 0;
+    table.clear();
+    int wg = 0;
+    for (const Active& a : active) {
+      table.push_back(make_task(a.r.p, arena_base + a.ws_off, a.phase, wg));
+      wg += table.back().nwg;
+    }
+    char* dtab = dev_tables[dev_next];
+    dev_next = (dev_next + 1) % (int)dev_tables.size();
+    const size_t tb = table.size() * sizeof(cqr2::StepTask);
+    rc = to_code(ring.copy(dtab, table.data(), tb, stream));
+    if (rc) return rc;
+    rc = to_code(cqr2::launch_step((const cqr2::StepTask*)dtab, (int)table.size(), wg, stream));
+    if (rc) return rc;
+    hipEvent_t ev = get_event();
+    if (ev == nullptr || hipEventRecord(ev, stream) != hipSuccess) return CQR2_ERR_HIP;
+    Finishing fin{ev, {}, {}};
+    std::vector<Active> still;
+    still.reserve(active.size());
+    for (Active& a : active) {
+      if (a.phase == cqr2::kStepPhases - 1) {
+        fin.reqs.push_back(a.r);
+        fin.offs.push_back(a.ws_off);
+      } else {
+        ++a.phase;
+        still.push_back(a);
+      }
+    }
+    active.swap(still);
+    if (fin.reqs.empty()) {
+      event_pool.push_back(ev);  // nothing waits on it; the stream order covers reuse
+    } else {
+      finishing.push_back(std::move(fin));
+    }
+    return 0;
+  }
+};
+
+extern "C" {
+
+size_t cqr2_batched_workspace_size(const cqr2_problem* probs, int32_t count, uint32_t flags) {
+  if (probs == nullptr || count < 0 || flags != CQR2_FP64) return 0;
+  size_t total = 0;
+  int64_t nsmall = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    if (cqr2_problem_check(&probs[i]) != 0) return 0;
+    total += problem_workspace(probs[i]);
+    if (probs[i].n > 0 && probs[i].n <= kStepMaxN) ++nsmall;
+  }
+  total += align_up((size_t)nsmall * cqr2::kStepPhases * sizeof(cqr2::StepTask));
+  return total ? total : kAlign;
+}
+
+int cqr2_factor_batched(const cqr2_problem* probs, int32_t count, void* work, size_t work_bytes, uint32_t flags,
+                        void* stream) {
+  if (count < 0) return -2;
+  if (count == 0) return 0;
+  if (probs == nullptr) return -1;
+  if (flags != CQR2_FP64) return -5;
+  for (int32_t i = 0; i < count; ++i)
+    if (cqr2_problem_check(&probs[i]) != 0) return -1;
+  if (work == nullptr || ((uintptr_t)work % kAlign) != 0) return -3;
+  if (work_bytes < cqr2_batched_workspace_size(probs, count, flags)) return -4;
+  hipStream_t s = (hipStream_t)stream;
+  // layout: task tables (6 phases), then one workspace per problem
+  std::vector<int32_t> small;
+  for (int32_t i = 0; i < count; ++i)
+    if (probs[i].n > 0 && probs[i].n <= kStepMaxN) small.push_back(i);
+  const size_t tab_bytes = align_up(small.size() * cqr2::kStepPhases * sizeof(cqr2::StepTask));
+  char* base = (char*)work;
+  std::vector<size_t> off(count);
+  size_t cur = tab_bytes;
+  for (int32_t i = 0; i < count; ++i) {
+    off[i] = cur;
+    cur += problem_workspace(probs[i]);
+  }
+  if (!small.empty()) {
+    std::vector<cqr2::StepTask> tabs;
+    std::vector<int> wgs(cqr2::kStepPhases, 0);
+    tabs.reserve(small.size() * cqr2::kStepPhases);
+    for (int ph = 0; ph < cqr2::kStepPhases; ++ph)
+      for (int32_t i : small) {
+        tabs.push_back(make_task(probs[i], base + off[i], ph, wgs[ph]));
+        wgs[ph] += tabs.back().nwg;
+      }
+    {
+      std::lock_guard<std::mutex> g(g_batched_mu);
+      if (g_batched_ring == nullptr) g_batched_ring = new TableRing(4);
+      const int rc = to_code(g_batched_ring->copy(base, tabs.data(), tabs.size() * sizeof(cqr2::StepTask), s));
+      if (rc) return rc;
+    }
+    const cqr2::StepTask* dt = (const cqr2::StepTask*)base;
+    for (int ph = 0; ph < cqr2::kStepPhases; ++ph) {
+      const int rc = to_code(cqr2::launch_step(dt + (size_t)ph * small.size(), (int)small.size(), wgs[ph], s));
+      if (rc) return rc;
+    }
+  }
+  for (int32_t i = 0; i < count; ++i) {
+    const cqr2_problem& p = probs[i];
+    if (p.n <= kStepMaxN) continue;
+    const cqr2::GeneralPlan plan = cqr2::plan_general(p.m, p.n, false);
+    const int rc = to_code(cqr2::factor_general(p.A, p.m, p.n, p.lda, p.Q, p.ldq, p.R, p.ldr, base + off[i], plan,
+                                                false, p.d_info, s, cqr2::TimerHook{}));
+    if (rc) return rc;
+  }
+  return 0;
+}
+
+int cqr2_server_create(size_t arena_bytes, size_t footprint_budget, int32_t max_active, void* stream,
+                       cqr2_server** out) {
+  if (out == nullptr) return -5;
+  *out = nullptr;
+  if (arena_bytes == 0) return -1;
+  if (max_active < 1 || max_active > 4096) return -3;
+  cqr2_server* sv = new cqr2_server();
+  sv->stream = (hipStream_t)stream;
+  sv->budget = footprint_budget;
+  sv->max_active = max_active;
+  arena_bytes = align_up(arena_bytes);
+  auto fail = [&](int code) {
+    cqr2_server_destroy(sv);
+    return code;
+  };
+  if (hipMalloc((void**)&sv->arena_base, arena_bytes) != hipSuccess) return fail(CQR2_ERR_HIP);
+  sv->arena.reset(arena_bytes);
+  if (hipStreamCreateWithFlags(&sv->large_stream, hipStreamNonBlocking) != hipSuccess) return fail(CQR2_ERR_HIP);
+  const size_t tb = align_up((size_t)max_active * sizeof(cqr2::StepTask));
+  for (int i = 0; i < 8; ++i) {
+    char* d = nullptr;
+    if (hipMalloc((void**)&d, tb) != hipSuccess) return fail(CQR2_ERR_HIP);
+    sv->dev_tables.push_back(d);
+  }
+  if (cqr2_server_clock(sv) != 0) return fail(CQR2_ERR_HIP);
+  *out = sv;
+  return 0;
+}
+
+int cqr2_server_destroy(cqr2_server* s) {
+  if (s == nullptr) return -1;
+  (void)hipStreamSynchronize(s->stream);
+  if (s->large_stream) {
+    (void)hipStreamSynchronize(s->large_stream);
+    (void)hipStreamDestroy(s->large_stream);
+  }
+  s->ring.release();
+  for (char* d : s->dev_tables) (void)hipFree(d);
+  for (auto& f : s->finishing) (void)hipEventDestroy(f.ev);
+  for (hipEvent_t e : s->event_pool) (void)hipEventDestroy(e);
+  if (s->t0) (void)hipEventDestroy(s->t0);
+  if (s->arena_base) (void)hipFree(s->arena_base);
+  delete s;
+  return 0;
+}
+
+int cqr2_server_clock(cqr2_server* s) {
+  if (s == nullptr) return -1;
+  if (s->t0 == nullptr && hipEventCreate(&s->t0) != hipSuccess) return CQR2_ERR_HIP;
+  if (hipEventRecord(s->t0, s->stream) != hipSuccess) return CQR2_ERR_HIP;
+  return hipEventSynchronize(s->t0) == hipSuccess ? 0 : CQR2_ERR_HIP;
+}
+
+int cqr2_server_submit(cqr2_server* s, const cqr2_problem* p, int64_t tag) {
+  if (s == nullptr) return -1;
+  if (p == nullptr || cqr2_problem_check(p) != 0) return -2;
+  if (p->n == 0) return -3;
+  cqr2_server::Req r{*p, tag, problem_workspace(*p), problem_footprint(*p), p->n > kStepMaxN};
+  if (r.ws_bytes > s->arena.size() || (s->budget && r.footprint > s->budget)) return CQR2_ERR_TOO_LARGE;
+  s->queue.push_back(r);
+  return 0;
+}
+
+int cqr2_server_step(cqr2_server* s, int32_t* n_active, int32_t* n_queued) {
+  if (s == nullptr) return -1;
+  const int rc = s->step();
+  if (n_active) *n_active = (int32_t)s->active.size() + s->n_large_running;
+  if (n_queued) *n_queued = (int32_t)s->queue.size();
+  return rc;
+}
+
+int cqr2_server_poll(cqr2_server* s, int64_t* tags, double* done_ms, int32_t max_count, int32_t* count) {
+  if (s == nullptr) return -1;
+  if (max_count < 0 || (max_count > 0 && (tags == nullptr || done_ms == nullptr))) return -4;
+  if (count == nullptr) return -5;
+  const int rc = s->reap();
+  if (rc) return rc;
+  const int32_t k = std::min<int32_t>(max_count, (int32_t)s->done.size());
+  for (int32_t i = 0; i < k; ++i) {
+    tags[i] = s->done[i].first;
+    done_ms[i] = s->done[i].second;
+  }
+  s->done.erase(s->done.begin(), s->done.begin() + k);
+  *count = k;
+  return 0;
+}
+
+}  // extern "C"

@@ -129,3 +129,63 @@ def test_binding_fails_loudly_without_library(tmp_path):
             mod.load(str(tmp_path / "missing.so"))
     finally:
         mod._lib = saved
+
+
+def _problem(**kw):
+    import paper_1710_08471_amd as cqm
+    base = dict(A=0x10000, Q=0x10000000, R=0x20000000, m=100, n=10, lda=100, ldq=100, ldr=10, d_info=None)
+    base.update(kw)
+    return cqm.Problem(base["A"], base["Q"], base["R"], base["m"], base["n"], base["lda"], base["ldq"],
+                       base["ldr"], base["d_info"])
+
+
+def test_problem_check_codes():
+    lib = cq.load()
+    chk = lambda **kw: lib.cqr2_problem_check(ctypes.byref(_problem(**kw)))
+    assert chk() == 0
+    assert chk(n=-1) == -3
+    assert chk(m=5) == -2
+    assert chk(lda=99) == -4
+    assert chk(ldq=99) == -6
+    assert chk(ldr=9) == -8
+    assert chk(d_info=0x30000002) == -11
+    assert chk(A=None) == -1
+    assert chk(A=0x10004) == -1
+    assert chk(Q=0x10000 + 80) == -5          # Q overlaps A
+    assert chk(R=0x10000000 + 8) == -7        # R overlaps Q
+    assert chk(m=40000, n=20000, lda=40000, ldq=40000, ldr=20000, R=0x80000000) == cq.CQR2_ERR_UNSUPPORTED
+    assert chk(n=0, A=None, Q=None, R=None) == 0
+
+
+def test_batched_argument_errors():
+    lib = cq.load()
+    probs = (cq.Problem * 2)(_problem(), _problem(A=0x40000000, Q=0x50000000, R=0x60000000, m=300, n=129,
+                                                   lda=300, ldq=300, ldr=129))
+    ws = lib.cqr2_batched_workspace_size(probs, 2, 0)
+    assert ws > 0 and ws % 256 == 0
+    assert lib.cqr2_batched_workspace_size(probs, 2, 1) == 0            # FP64 only
+    assert ws > lib.cqr2_batched_workspace_size(probs, 1, 0) > 0
+    W = ctypes.c_void_p(0x70000000)
+    f = lib.cqr2_factor_batched
+    assert f(probs, -1, W, ws, 0, NULL) == -2
+    assert f(probs, 0, W, ws, 0, NULL) == 0                               # nothing to do
+    assert f(probs, 2, W, ws, 1, NULL) == -5
+    assert f(probs, 2, NULL, ws, 0, NULL) == -3
+    assert f(probs, 2, ctypes.c_void_p(0x70000008), ws, 0, NULL) == -3  # not 256-byte aligned
+    assert f(probs, 2, W, ws - 1, 0, NULL) == -4
+    bad = (cq.Problem * 2)(_problem(), _problem(lda=5))
+    assert f(bad, 2, W, ws, 0, NULL) == -1
+    assert lib.cqr2_batched_workspace_size(bad, 2, 0) == 0
+
+
+def test_server_argument_errors():
+    lib = cq.load()
+    h = ctypes.c_void_p()
+    assert lib.cqr2_server_create(0, 0, 8, NULL, ctypes.byref(h)) == -1
+    assert lib.cqr2_server_create(1 << 20, 0, 0, NULL, ctypes.byref(h)) == -3
+    assert lib.cqr2_server_create(1 << 20, 0, 5000, NULL, ctypes.byref(h)) == -3
+    assert lib.cqr2_server_create(1 << 20, 0, 8, NULL, None) == -5
+    assert lib.cqr2_server_submit(NULL, ctypes.byref(_problem()), 0) == -1
+    assert lib.cqr2_server_step(NULL, None, None) == -1
+    assert lib.cqr2_server_clock(NULL) == -1
+    assert lib.cqr2_server_destroy(NULL) == -1
