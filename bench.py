@@ -120,6 +120,88 @@ def cpu_baseline(a, budget_s: float):
     }
 
 
+# Served stream (2000 requests of uneven shape, Poisson arrivals at a fixed
+# rate); the rate is pinned at about half the measured closed-loop capacity.
+SERVE_REQUESTS = 2000
+SERVE_SEED = 5
+SERVE_RATE = 2500.0            # requests per second (open loop), about 0.45 of the closed-loop capacity
+SERVE_ARENA = 16 << 30         # workspace arena of the server, bytes
+SERVE_BUDGET = 64 << 30        # in-flight footprint budget (A, Q, R, workspace), bytes
+SERVE_SLOTS = 256
+
+
+def serve_stream(cq, torch, count: int, rate: float, seed: int):
+    """Closed-loop capacity and open-loop latency of the continuous-batching
+    server on the request mix; a sample of results is checked against the
+    CPU oracle on the same input bytes."""
+    import numpy as np
+
+    import oracle
+    from synth import gdv_matrix_device, request_mix
+
+    reqs = request_mix(count, rate, seed)
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    mats = [gdv_matrix_device(r.m, r.n, r.kappa, r.seed, device=dev) for r in reqs]
+    qs = [cq.empty_colmajor(r.m, r.n, device=dev) for r in reqs]
+    rs = [cq.empty_colmajor(r.n, r.n, device=dev) for r in reqs]
+    torch.cuda.synchronize()
+    total_a = sum(r.m * r.n * 8 for r in reqs)
+    log(f"serving: {count} requests generated on the device in {time.perf_counter() - t0:.1f} s "
+        f"({total_a / 1e9:.1f} GB of A)")
+
+    def run(arrivals_ms):
+        done = {}
+        steps = 0
+        with cq.Server(SERVE_ARENA, SERVE_BUDGET, SERVE_SLOTS) as sv:
+            sv.clock()
+            h0 = time.perf_counter()
+            i = 0
+            while len(done) < count:
+                now = (time.perf_counter() - h0) * 1e3
+                while i < count and arrivals_ms[i] <= now:
+                    sv.submit(i, mats[i], qs[i], rs[i])
+                    i += 1
+                sv.step()
+                steps += 1
+                for tag, ms in sv.poll():
+                    done[tag] = ms
+        lat = np.array([done[k] - arrivals_ms[k] for k in range(count)])
+        span = max(done.values()) - min(arrivals_ms)
+        return {"solves_per_s": round(count / (span / 1e3), 1), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                "p99_ms": round(float(np.percentile(lat, 99)), 3), "makespan_ms": round(span, 2),
+                "host_steps": steps}
+
+    closed = run([0.0] * count)
+    log(f"serving closed loop: {closed}")
+    opened = run([r.arrival_s * 1e3 for r in reqs])
+    log(f"serving open loop at {rate:.0f}/s: {opened}")
+    # the same stream time-compressed to 0.8 of the measured capacity
+    hi_rate = round(0.8 * closed["solves_per_s"], -2)
+    scale = rate / hi_rate if hi_rate > 0 else 1.0
+    high = run([r.arrival_s * 1e3 * scale for r in reqs])
+    high["rate_per_s"] = hi_rate
+    log(f"serving open loop at {hi_rate:.0f}/s: {high}")
+
+    # oracle check on the first request of every n in the mix
+    checked = []
+    for nn in sorted({r.n for r in reqs}):
+        k = next(r.idx for r in reqs if r.n == nn)
+        a = mats[k].cpu().numpy()
+        q, r_ = qs[k].cpu().numpy(), rs[k].cpu().numpy()
+        q_ref, r_ref = oracle.cqr2(a)
+        ok = (oracle.orthogonality(q) <= 1e-12 and oracle.residual(a, q, r_) <= 1e-13
+              and oracle.rel_fro(r_, r_ref) <= 1e-9)
+        checked.append({"request": k, "m": reqs[k].m, "n": nn, "ok": bool(ok)})
+    return {
+        "requests": count, "rate_per_s": rate, "seed": seed,
+        "mix": "m log-uniform [1024,131072], n in {16,32,64,128,256}, kappa log-uniform [1e1,1e6]",
+        "solves_per_s": opened["solves_per_s"], "p50_ms": opened["p50_ms"], "p99_ms": opened["p99_ms"],
+        "closed_loop": closed, "open_loop": opened, "open_loop_0.8C": high, "oracle_sample": checked,
+        "slots": SERVE_SLOTS, "arena_bytes": SERVE_ARENA, "footprint_budget": SERVE_BUDGET,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -133,6 +215,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="also run a device copy of this many GiB (counter calibration under rocprofv3)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served-stream measurement")
+    ap.add_argument("--serve-only", action="store_true", help="only the served-stream measurement")
+    ap.add_argument("--serve-requests", type=int, default=SERVE_REQUESTS)
+    ap.add_argument("--serve-rate", type=float, default=SERVE_RATE)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -143,6 +229,16 @@ def main():
 
     import paper_1710_08471_amd as cq
     from synth import WORKLOADS, workload_matrix
+
+    if args.serve_only:
+        cq.load()
+        out = {"metric": "served solves/s, p99 latency", "unit": "solves/s", "n_gpus": 1, "data": "synthetic",
+               "higher_is_better": True, "dtype": "f64"}
+        sv = serve_stream(cq, torch, args.serve_requests, args.serve_rate, SERVE_SEED)
+        out["value"] = sv["solves_per_s"]
+        out["serving"] = sv
+        print(json.dumps(out), flush=True)
+        return
 
     wl = WORKLOADS[args.workload]
     m, n = wl.m, wl.n
@@ -269,6 +365,8 @@ def main():
         roof["avg_launch_ms"] = round(avg_ms, 5)
         roof["algorithmic_per_launch"] = by if bound == "hbm" else fl
         out["roofline"] = roof
+    if default_run and not args.no_serve:
+        out["serving"] = serve_stream(cq, torch, args.serve_requests, args.serve_rate, SERVE_SEED)
     if default_run and not args.no_cpu_baseline:
         log("timing the CPU oracle ...")
         out["cpu_baseline"] = cpu_baseline(a_host, args.cpu_budget)

@@ -182,8 +182,10 @@ struct cqr2_server {
     std::vector<size_t> offs;
   };
 
-  hipStream_t stream = nullptr;       // steps
-  hipStream_t large_stream = nullptr; // n > 128 requests
+  static constexpr int kLargeStreams = 4;
+  hipStream_t stream = nullptr;              // steps
+  hipStream_t large[kLargeStreams] = {};     // n > 128 requests, round robin
+  int large_next = 0;
   char* arena_base = nullptr;
   Arena arena;
   size_t budget = 0, in_flight_bytes = 0;
@@ -247,11 +249,13 @@ struct cqr2_server {
       } else {
         const cqr2_problem& p = r.p;
         const cqr2::GeneralPlan plan = cqr2::plan_general(p.m, p.n, false);
+        hipStream_t ls = large[large_next];
+        large_next = (large_next + 1) % kLargeStreams;
         hipError_t e = cqr2::factor_general(p.A, p.m, p.n, p.lda, p.Q, p.ldq, p.R, p.ldr, arena_base + off, plan,
-                                            false, p.d_info, large_stream, cqr2::TimerHook{});
+                                            false, p.d_info, ls, cqr2::TimerHook{});
         if (e != hipSuccess) return CQR2_ERR_HIP;
         hipEvent_t ev = get_event();
-        if (ev == nullptr || hipEventRecord(ev, large_stream) != hipSuccess) return CQR2_ERR_HIP;
+        if (ev == nullptr || hipEventRecord(ev, ls) != hipSuccess) return CQR2_ERR_HIP;
         ++n_large_running;
         finishing.push_back({ev, {r}, {off}});
       }
@@ -390,7 +394,8 @@ int cqr2_server_create(size_t arena_bytes, size_t footprint_budget, int32_t max_
   };
   if (hipMalloc((void**)&sv->arena_base, arena_bytes) != hipSuccess) return fail(CQR2_ERR_HIP);
   sv->arena.reset(arena_bytes);
-  if (hipStreamCreateWithFlags(&sv->large_stream, hipStreamNonBlocking) != hipSuccess) return fail(CQR2_ERR_HIP);
+  for (auto& ls : sv->large)
+    if (hipStreamCreateWithFlags(&ls, hipStreamNonBlocking) != hipSuccess) return fail(CQR2_ERR_HIP);
   const size_t tb = align_up((size_t)max_active * sizeof(cqr2::StepTask));
   for (int i = 0; i < 8; ++i) {
     char* d = nullptr;
@@ -405,10 +410,11 @@ int cqr2_server_create(size_t arena_bytes, size_t footprint_budget, int32_t max_
 int cqr2_server_destroy(cqr2_server* s) {
   if (s == nullptr) return -1;
   (void)hipStreamSynchronize(s->stream);
-  if (s->large_stream) {
-    (void)hipStreamSynchronize(s->large_stream);
-    (void)hipStreamDestroy(s->large_stream);
-  }
+  for (auto& ls : s->large)
+    if (ls) {
+      (void)hipStreamSynchronize(ls);
+      (void)hipStreamDestroy(ls);
+    }
   s->ring.release();
   for (char* d : s->dev_tables) (void)hipFree(d);
   for (auto& f : s->finishing) (void)hipEventDestroy(f.ev);

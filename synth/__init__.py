@@ -6,6 +6,7 @@ the factorization's arithmetic.  See ``synth.matrices``.
 from .matrices import (  # noqa: F401
     WORKLOADS,
     gdv_matrix,
+    gdv_matrix_device,
     integer_matrix,
     request_mix,
     scaled_gaussian,

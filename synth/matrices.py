@@ -135,3 +135,27 @@ def request_mix(count: int, rate_per_s: float, seed: int,
             t += arr.exponential(1.0 / rate_per_s)
         out.append(Request(i, m, n, kappa, seed * 100003 + i, t))
     return out
+
+
+def gdv_matrix_device(m: int, n: int, kappa: float, seed: int, device="cuda"):
+    """A = G diag(logspace(0, -log10 kappa, n)) V generated on a torch device.
+
+    Same construction as ``gdv_matrix`` with torch's seeded generator of that
+    device (so the bytes differ from the host version); used where thousands
+    of request matrices are needed quickly (the served stream).  G and V are
+    the orthonormal factors of seeded Gaussians (torch.linalg.qr).  Returns a
+    column-major (strides (1, m)) float64 tensor.
+    """
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    g = torch.randn((n, m), generator=gen, device=device, dtype=torch.float64).t()
+    g = torch.linalg.qr(g, mode="reduced").Q
+    v = torch.randn((n, n), generator=gen, device=device, dtype=torch.float64)
+    v = torch.linalg.qr(v, mode="reduced").Q
+    d = torch.logspace(0.0, -math.log10(kappa), n, dtype=torch.float64, device=device) if n > 1 else \
+        torch.ones(1, dtype=torch.float64, device=device)
+    a = (g * d[None, :]) @ v
+    out = torch.empty((n, m), dtype=torch.float64, device=device).t()
+    out.copy_(a)
+    return out
