@@ -300,6 +300,7 @@ int cqr2_factor(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, d
 size_t cqr2_gram_workspace_size(int64_t m, int64_t n) {
   if (m < 0 || n < 1 || n > CQR2_MAX_N) return 0;
   if (n <= kSmallN) return align_up(cqr2::plan_gram(m, n).partial_bytes);
+  if (n <= cqr2::kWideMaxN) return align_up(cqr2::plan_gram_wide(m).partial_bytes);
   const int splits = cqr2::gemm_pick_splits(n, n, m, cqr2::kPlanCUs);
   return align_up(cqr2::gemm_workspace_bytes(n, n, splits) + 8);
 }
@@ -328,7 +329,13 @@ int cqr2_gram(const double* A, int64_t m, int64_t n, int64_t lda, double* W, int
     CQR2_TRY(cqr2::launch_gram_reduce(p, (const double*)work, (int)n, W, ldw, nullptr, s));
     return 0;
   }
-  // n > 128: lower triangle by the GEMM, then mirrored.
+  if (n <= cqr2::kWideMaxN) {
+    CQR2_TRY(cqr2::launch_gram_wide(cqr2::plan_gram_wide(m), 0, A, m, (int)n, lda, (double*)work, W, ldw, nullptr,
+                                    s));
+    CQR2_TRY(cqr2::launch_mirror_lower(W, ldw, n, s));
+    return 0;
+  }
+  // n > 256: lower triangle by the GEMM, then mirrored.
   const int splits = cqr2::gemm_pick_splits(n, n, m, cqr2::kPlanCUs);
   CQR2_TRY(cqr2::launch_gemm(1, 0, n, n, m, 1.0, A, lda, A, lda, 0.0, W, ldw, cqr2::GEMM_C_LOWER, splits,
                              (double*)work, nullptr, s));
@@ -391,6 +398,14 @@ int cqr2_apply_rinv(const double* A, int64_t m, int64_t n, int64_t lda, const do
   hipStream_t s = (hipStream_t)stream;
   if (n <= kSmallN) {
     CQR2_TRY(cqr2::launch_apply_rinv(A, m, (int)n, lda, U, 1, ldu, Q, ldq, nullptr, device_cus(), s));
+    return 0;
+  }
+  if (n <= cqr2::kWideMaxN) {  // each workgroup reads only the rows it writes: in place is safe
+    int err = 0;
+    double* ut = (double*)cached_workspace(cqr2::kUpperImageBytes, &err);
+    if (err) return err;
+    CQR2_TRY(cqr2::launch_upper_image(U, ldu, (int)n, ut, s));  // row-major image of U
+    CQR2_TRY(cqr2::launch_tall_gemm(0, A, m, (int)n, lda, ut, Q, ldq, nullptr, s));
     return 0;
   }
   const double* src = A;

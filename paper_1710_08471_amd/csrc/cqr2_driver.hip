@@ -157,7 +157,9 @@ GeneralPlan plan_general(int64_t m, int64_t n, bool mixed) {
   p.off_r2 = take(nn);
   p.off_ri2 = take(nn);
   p.off_p = take(nn);
-  const size_t gws = gemm_workspace_bytes(n, n, p.gram_splits);
+  p.off_uimg = n <= kWideMaxN ? take(kUpperImageBytes) : 0;
+  size_t gws = gemm_workspace_bytes(n, n, p.gram_splits);
+  if (n <= kWideMaxN) gws = plan_gram_wide(m).partial_bytes;
   const size_t rws = cholinv_rec_workspace(n);
   p.off_scratch = take(gws > rws ? gws : rws);
   p.off_q1 = take((size_t)m * n * (mixed ? sizeof(float) : sizeof(double)));
@@ -175,35 +177,56 @@ hipError_t factor_general(const double* A, int64_t m, int64_t n, int64_t lda, do
   double* R2 = (double*)(ws + p.off_r2);
   double* Ri2 = (double*)(ws + p.off_ri2);
   double* P = (double*)(ws + p.off_p);
+  double* Uimg = (double*)(ws + p.off_uimg);
   char* scratch = ws + p.off_scratch;
   void* Q1 = ws + p.off_q1;
   const int q1f = mixed ? 1 : 0;  // element type of the stored Q1
+  // n <= 256: tall-skinny kernels (A read once per step); above: tiled GEMMs
+  const bool wide = n <= kWideMaxN;
+  const WideGramPlan wp = plan_gram_wide(m);
   CQR2_HIP(launch_set_info(info, 0, s));
   // pass 1: CQR(A) -> Q1 (workspace), R1
   th.begin(0, s);
-  CQR2_HIP(launch_gemm(1, 0, n, n, m, 1.0, A, lda, A, lda, 0.0, W, n, GEMM_C_LOWER, p.gram_splits, (double*)scratch,
-                       info, s));
+  if (wide)
+    CQR2_HIP(launch_gram_wide(wp, 0, A, m, (int)n, lda, (double*)scratch, W, n, info, s));
+  else
+    CQR2_HIP(launch_gemm(1, 0, n, n, m, 1.0, A, lda, A, lda, 0.0, W, n, GEMM_C_LOWER, p.gram_splits,
+                         (double*)scratch, info, s));
   th.end(0, s);
   th.begin(2, s);
   CQR2_HIP(cholinv_recursive(W, n, n, R1, n, Ri1, n, scratch, info, 0, s));
   th.end(2, s);
   th.begin(3, s);
-  if (mixed)
+  // the tall kernels read R^{-1} as its zero-padded row-major image
+  if (wide) CQR2_HIP(launch_upper_image(Ri1, n, (int)n, Uimg, s));
+  if (mixed && wide)
+    CQR2_HIP(launch_tall_gemm_f32(A, m, (int)n, lda, Uimg, (float*)Q1, m, info, s));
+  else if (mixed)
     CQR2_HIP(launch_gemm_f32(0, 0, m, n, n, A, lda, Ri1, n, (float*)Q1, m, GEMM_B_UPPER, info, s));
+  else if (wide)
+    CQR2_HIP(launch_tall_gemm(0, A, m, (int)n, lda, Uimg, (double*)Q1, m, info, s));
   else
     CQR2_HIP(launch_gemm(0, 0, m, n, n, 1.0, A, lda, Ri1, n, 0.0, (double*)Q1, m, GEMM_B_UPPER, 1, nullptr, info, s));
   th.end(3, s);
   // pass 2: CQR(Q1) -> Q, R2, on the stored Q1 values (FP32 ones widen exactly)
   th.begin(0, s);
-  CQR2_HIP(launch_gemm_in32(q1f, q1f, 1, 0, n, n, m, 1.0, Q1, m, Q1, m, 0.0, W, n, GEMM_C_LOWER, p.gram_splits,
-                            (double*)scratch, info, s));
+  if (wide)
+    CQR2_HIP(launch_gram_wide(wp, q1f, Q1, m, (int)n, m, (double*)scratch, W, n, info, s));
+  else
+    CQR2_HIP(launch_gemm_in32(q1f, q1f, 1, 0, n, n, m, 1.0, Q1, m, Q1, m, 0.0, W, n, GEMM_C_LOWER, p.gram_splits,
+                              (double*)scratch, info, s));
   th.end(0, s);
   th.begin(2, s);
   CQR2_HIP(cholinv_recursive(W, n, n, R2, n, Ri2, n, scratch, info, (int)n, s));
   th.end(2, s);
   th.begin(4, s);
-  CQR2_HIP(launch_gemm_in32(q1f, 0, 0, 0, m, n, n, 1.0, Q1, m, Ri2, n, 0.0, Q, ldq, GEMM_B_UPPER, 1, nullptr, info,
-                            s));
+  if (wide) {
+    CQR2_HIP(launch_upper_image(Ri2, n, (int)n, Uimg, s));
+    CQR2_HIP(launch_tall_gemm(q1f, Q1, m, (int)n, m, Uimg, Q, ldq, info, s));
+  }
+  else
+    CQR2_HIP(launch_gemm_in32(q1f, 0, 0, 0, m, n, n, 1.0, Q1, m, Ri2, n, 0.0, Q, ldq, GEMM_B_UPPER, 1, nullptr,
+                              info, s));
   th.end(4, s);
   // R = R2 R1
   th.begin(5, s);

@@ -87,6 +87,29 @@ hipError_t launch_gemm_f32(int transA, int transB, int64_t M, int64_t N, int64_t
                            const double* B, int64_t ldb, float* C, int64_t ldc, int flags, const int32_t* info,
                            hipStream_t s);
 
+// ---- tall-skinny kernels for 128 < n <= 256 --------------------------------
+constexpr int64_t kWideMaxN = 256;
+struct WideGramPlan {
+  int64_t stages = 0, stages_per_wg = 0;  // 32-row stages
+  int splits = 0;
+  size_t partial_bytes = 0;
+};
+WideGramPlan plan_gram_wide(int64_t m);
+// Lower triangle of W = AᵀA (n <= 256); A is FP64, or FP32 when a_f32.
+hipError_t launch_gram_wide(const WideGramPlan& p, int a_f32, const void* A, int64_t m, int n, int64_t lda,
+                            double* partials, double* W, int64_t ldw, const int32_t* info, hipStream_t s);
+// Zero-padded 256 x 256 row-major image of the upper triangle of X (n x n,
+// column-major, ldx): the form of U the tall kernels read.
+constexpr int64_t kUpperImageBytes = 256 * 256 * sizeof(double);
+hipError_t launch_upper_image(const double* X, int64_t ldx, int n, double* T, hipStream_t s);
+// Q = A U (n <= 256, U given as its upper image); A FP64 or FP32 (a_f32), FP64
+// arithmetic.
+hipError_t launch_tall_gemm(int a_f32, const void* A, int64_t m, int n, int64_t lda, const double* Uimg, double* Q,
+                            int64_t ldq, const int32_t* info, hipStream_t s);
+// Q(float) = fl32(A) fl32(U) with FP32 products and sums (n <= 256).
+hipError_t launch_tall_gemm_f32(const double* A, int64_t m, int n, int64_t lda, const double* Uimg, float* Q,
+                                int64_t ldq, const int32_t* info, hipStream_t s);
+
 // ---- recursive CholInv and the n > 128 driver --------------------------------
 int64_t cholinv_split(int64_t n);
 size_t cholinv_rec_workspace(int64_t n);
@@ -102,8 +125,8 @@ hipError_t launch_mirror_lower(double* W, int64_t ldw, int64_t n, hipStream_t s)
 
 struct GeneralPlan {
   int gram_splits = 1, apply_splits = 1;
-  size_t off_info = 0, off_w = 0, off_r1 = 0, off_ri1 = 0, off_r2 = 0, off_ri2 = 0, off_p = 0, off_scratch = 0,
-         off_q1 = 0;
+  size_t off_info = 0, off_w = 0, off_r1 = 0, off_ri1 = 0, off_r2 = 0, off_ri2 = 0, off_p = 0, off_uimg = 0,
+         off_scratch = 0, off_q1 = 0;
   size_t total = 0;
 };
 // mixed: pass 1's Q1 = A R1^-1 is formed with FP32 products and sums and kept

@@ -1,0 +1,495 @@
+// Tall-skinny kernels for 128 < n <= 256 (the same steps as the n <= 128
+// kernels, at twice the width):
+//   k_gram_wide     partial Grams W = AᵀA over row blocks (Syrk; Algorithm 4
+//                   step 1), all lower 16 x 16 tiles of one workgroup's rows
+//                   held in registers, A read once;
+//   k_gram_wide_reduce  fixed-order sum of the partials into W (lower);
+//   k_tall          Q = A U for upper-triangular U (Algorithm 4 step 3), one
+//                   128 x 256 output tile per workgroup, A read once; FP64
+//                   arithmetic, or FP32 products and sums into an FP32 Q
+//                   (pass 1 of the mixed-precision form).
+#include "cqr2_internal.h"
+
+#include <hip/hip_runtime.h>
+#include <cmath>
+#include <cstdint>
+
+namespace cqr2 {
+
+// ============================================================================
+// Gram, 128 < n <= 256: v_mfma_f64_16x16x4f64.
+//
+// Operands per lane l: A-operand (row l%16, k l/16), B-operand (k l/16,
+// column l%16); result entry r of lane l is D(4r + l/16, l%16).  With the
+// "fragment" f_c(l) = A(k0 + l/16, 16c + l%16) of a 4-row step, the tile
+// (I, J) of W accumulates mfma(f_I, f_J).  The 16 x 17 / 2 = 136 lower tiles
+// are dealt to 8 waves by tile rows in snake order (rows w and 15 - w, 17
+// tiles each); a wave keeps its 17 accumulators (4 doubles per lane each)
+// for its whole row range.
+//
+// A streams through LDS in 32-row stages (column-major, 32 doubles per
+// column, rows of column c stored XOR 2 (c & 15), so the 16 lanes of a
+// fragment row hit 16 distinct bank pairs; the XOR is even, so the row pairs
+// of the 16-byte direct loads stay adjacent).  Double-buffered: 2 x 64 KB.
+// An FP32 input (mixed precision's Q1) is staged as FP32 and widened exactly
+// when a fragment is read.
+// ============================================================================
+constexpr int kWideRows = 32;
+constexpr int kWideCols = 256;
+constexpr int kWideTiles = kWideCols / 16;                        // 16
+constexpr int kWideLower = kWideTiles * (kWideTiles + 1) / 2;     // 136
+constexpr int kWideWaves = 8;
+constexpr int kWideBuf = kWideCols * kWideRows;                   // doubles per stage
+constexpr int kWideSplits = 256;
+
+__device__ __forceinline__ int wide_pos(int c, int r) { return c * kWideRows + (r ^ ((c & 15) << 1)); }
+// FP32 stages (Q1 of the mixed-precision form): 32 floats per column, rows
+// XOR 4 ((c >> 1) & 7), which keeps the 4-row groups of the 16-byte copies
+// together and spreads a fragment row's 16 columns over 16 distinct banks.
+__device__ __forceinline__ int wide_pos_f(int c, int r) { return c * kWideRows + (r ^ (((c >> 1) & 7) << 2)); }
+template <typename TA>
+__device__ __forceinline__ int wide_slot(int c, int r) {
+  if constexpr (sizeof(TA) == 8) return wide_pos(c, r);
+  else return wide_pos_f(c, r);
+}
+
+typedef double wd4 __attribute__((ext_vector_type(4)));
+
+template <int W>
+struct WideWave {
+  static constexpr int I0 = W, I1 = kWideTiles - 1 - W;
+  static constexpr int NT = (I0 + 1) + (I1 + 1);   // tiles of this wave
+  static constexpr int NF = I1 + 1;                 // fragments needed (columns tiles 0..I1)
+  static constexpr int tile_i(int t) { return t <= I0 ? I0 : I1; }
+  static constexpr int tile_j(int t) { return t <= I0 ? t : t - (I0 + 1); }
+};
+
+template <typename TA, int W>
+__device__ __forceinline__ void gram_wide_wave(const TA* __restrict__ A, int64_t m, int n, int64_t lda,
+                                               int64_t st0, int64_t st1, bool direct_ok, TA* lds,
+                                               double* __restrict__ out) {
+  using WW = WideWave<W>;
+  const int tid = threadIdx.x, lane = tid & 63;
+  wd4 acc[WW::NT];
+#pragma unroll
+  for (int t = 0; t < WW::NT; ++t) acc[t] = wd4{0.0, 0.0, 0.0, 0.0};
+
+  for (int e = tid; e < 2 * kWideBuf; e += 64 * kWideWaves)
+    if ((e % kWideBuf) / kWideRows >= n) lds[e] = (TA)0;
+  auto fill = [&](int64_t st, TA* buf) {
+    const int64_t row0 = st * kWideRows;
+    if (direct_ok && row0 + kWideRows <= m) {
+      if constexpr (sizeof(TA) == 8) {
+        // one instruction: 4 columns x 32 rows; lane i -> column 4p + (i>>4), LDS rows 2(i&15), +1
+        const int sub = lane >> 4, lrow = 2 * (lane & 15);
+        for (int p = W; p < kWideCols / 4; p += kWideWaves) {
+          const int col = 4 * p + sub;
+          if (col < n) {
+            const int grow = lrow ^ ((col & 15) << 1);
+            __builtin_amdgcn_global_load_lds((const void*)(A + row0 + grow + (int64_t)col * lda),
+                                             (__attribute__((address_space(3))) void*)(buf + 4 * p * kWideRows),
+                                             16, 0, 0);
+          }
+        }
+      } else {
+        // one instruction: 8 columns x 32 rows; lane i -> column 8p + (i>>3), LDS rows 4(i&7) .. +3
+        const int sub = lane >> 3, lrow = 4 * (lane & 7);
+        for (int p = W; p < kWideCols / 8; p += kWideWaves) {
+          const int col = 8 * p + sub;
+          if (col < n) {
+            const int grow = lrow ^ (((col >> 1) & 7) << 2);
+            __builtin_amdgcn_global_load_lds((const void*)(A + row0 + grow + (int64_t)col * lda),
+                                             (__attribute__((address_space(3))) void*)(buf + 8 * p * kWideRows),
+                                             16, 0, 0);
+          }
+        }
+      }
+    } else {
+      for (int e = tid; e < kWideBuf; e += 64 * kWideWaves) {
+        const int c = e / kWideRows, r = e % kWideRows;
+        const int64_t row = row0 + r;
+        buf[wide_slot<TA>(c, r)] = (row < m && c < n) ? A[row + (int64_t)c * lda] : (TA)0;
+      }
+    }
+  };
+  if (st0 < st1) fill(st0, lds);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+
+  const int fc = lane & 15, fk = lane >> 4;
+  for (int64_t st = st0; st < st1; ++st) {
+    const int cur = (int)((st - st0) & 1);
+    TA* bcur = lds + cur * kWideBuf;
+    if (st + 1 < st1) fill(st + 1, lds + (cur ^ 1) * kWideBuf);
+#pragma unroll 1
+    for (int k0 = 0; k0 < kWideRows; k0 += 4) {
+      double f[WW::NF];
+#pragma unroll
+      for (int c = 0; c < WW::NF; ++c) f[c] = (double)bcur[wide_slot<TA>(16 * c + fc, k0 + fk)];
+#pragma unroll
+      for (int t = 0; t < WW::NT; ++t)
+        if (16 * WW::tile_i(t) < n)  // uniform: tiles past column n stay zero
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(f[WW::tile_i(t)], f[WW::tile_j(t)], acc[t], 0, 0, 0);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+  }
+  // tile (I, J) -> lower-order index I (I+1)/2 + J; 4 x 64 doubles, lane-major
+#pragma unroll
+  for (int t = 0; t < WW::NT; ++t) {
+    const int I = WW::tile_i(t), J = WW::tile_j(t);
+    double* o = out + (int64_t)(I * (I + 1) / 2 + J) * 256;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) o[r * 64 + lane] = acc[t][r];
+  }
+}
+
+template <typename TA>
+__global__ __launch_bounds__(64 * kWideWaves, 1) void k_gram_wide(const TA* __restrict__ A, int64_t m, int n,
+                                                                  int64_t lda, int64_t stages, int64_t spw,
+                                                                  double* __restrict__ partials,
+                                                                  const int32_t* __restrict__ info) {
+  __shared__ __attribute__((aligned(16))) TA lds[2 * kWideBuf];
+  if (info != nullptr && *info != 0) return;
+  const int64_t st0 = (int64_t)blockIdx.x * spw;
+  const int64_t st1 = st0 + spw < stages ? st0 + spw : stages;
+  // 16-byte copies: A aligned and every column start aligned
+  const bool direct_ok = (((uintptr_t)A & 15u) == 0) && (((lda * (int64_t)sizeof(TA)) & 15) == 0);
+  double* out = partials + (int64_t)blockIdx.x * kWideLower * 256;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  switch (wave) {
+    case 0: gram_wide_wave<TA, 0>(A, m, n, lda, st0, st1, direct_ok, lds, out); break;
+    case 1: gram_wide_wave<TA, 1>(A, m, n, lda, st0, st1, direct_ok, lds, out); break;
+    case 2: gram_wide_wave<TA, 2>(A, m, n, lda, st0, st1, direct_ok, lds, out); break;
+    case 3: gram_wide_wave<TA, 3>(A, m, n, lda, st0, st1, direct_ok, lds, out); break;
+    case 4: gram_wide_wave<TA, 4>(A, m, n, lda, st0, st1, direct_ok, lds, out); break;
+    case 5: gram_wide_wave<TA, 5>(A, m, n, lda, st0, st1, direct_ok, lds, out); break;
+    case 6: gram_wide_wave<TA, 6>(A, m, n, lda, st0, st1, direct_ok, lds, out); break;
+    case 7: gram_wide_wave<TA, 7>(A, m, n, lda, st0, st1, direct_ok, lds, out); break;
+    default: break;
+  }
+}
+
+// Sum of the partials in split order (8 contiguous sub-ranges added in
+// order), written to the lower triangle of W (n x n, ldw).
+__global__ __launch_bounds__(256) void k_gram_wide_reduce(const double* __restrict__ part, int splits, int n,
+                                                          double* __restrict__ W, int64_t ldw,
+                                                          const int32_t* __restrict__ info) {
+  __shared__ double red[8][32];
+  if (info != nullptr && *info != 0) return;
+  const int lanei = threadIdx.x & 31, sub = threadIdx.x >> 5;
+  constexpr int total = kWideLower * 256;
+  const int e = blockIdx.x * 32 + lanei;
+  double v = 0.0;
+  if (e < total) {
+    const int s0 = (splits * sub) / 8, s1 = (splits * (sub + 1)) / 8;
+    for (int s = s0; s < s1; ++s) v += part[(int64_t)s * total + e];
+  }
+  red[sub][lanei] = v;
+  __syncthreads();
+  if (sub != 0 || e >= total) return;
+  double t = red[0][lanei];
+#pragma unroll
+  for (int k = 1; k < 8; ++k) t += red[k][lanei];
+  const int tile = e >> 8, r = (e >> 6) & 3, l = e & 63;
+  int I = 0;
+  while ((I + 1) * (I + 2) / 2 <= tile) ++I;
+  const int J = tile - I * (I + 1) / 2;
+  const int row = 16 * I + 4 * r + (l >> 4), col = 16 * J + (l & 15);
+  if (row >= col && row < n) W[row + (int64_t)col * ldw] = t;
+}
+
+WideGramPlan plan_gram_wide(int64_t m) {
+  WideGramPlan p{};
+  p.stages = m > 0 ? (m + kWideRows - 1) / kWideRows : 1;
+  int64_t s = p.stages / 4;  // at least 4 stages per workgroup
+  if (s < 1) s = 1;
+  if (s > kWideSplits) s = kWideSplits;
+  p.stages_per_wg = (p.stages + s - 1) / s;
+  p.splits = (int)((p.stages + p.stages_per_wg - 1) / p.stages_per_wg);
+  p.partial_bytes = (size_t)p.splits * kWideLower * 256 * sizeof(double);
+  return p;
+}
+
+hipError_t launch_gram_wide(const WideGramPlan& p, int a_f32, const void* A, int64_t m, int n, int64_t lda,
+                            double* partials, double* W, int64_t ldw, const int32_t* info, hipStream_t s) {
+  if (n > kWideCols) return hipErrorInvalidValue;
+  if (a_f32)
+    hipLaunchKernelGGL(k_gram_wide<float>, dim3(p.splits), dim3(64 * kWideWaves), 0, s, (const float*)A, m, n, lda,
+                       p.stages, p.stages_per_wg, partials, info);
+  else
+    hipLaunchKernelGGL(k_gram_wide<double>, dim3(p.splits), dim3(64 * kWideWaves), 0, s, (const double*)A, m, n,
+                       lda, p.stages, p.stages_per_wg, partials, info);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int total = kWideLower * 256;
+  hipLaunchKernelGGL(k_gram_wide_reduce, dim3((total + 31) / 32), dim3(256), 0, s, partials, p.splits, n, W, ldw,
+                     info);
+  return hipGetLastError();
+}
+
+// ============================================================================
+// Q = A U for upper-triangular U, n <= 256 (Algorithm 4 step 3).
+//
+// U comes as a zero-padded 256 x 256 row-major image (U(k, j) at U[256 k + j],
+// zero outside the n x n upper triangle), so a chunk of 16 rows of U is
+// 32 KB of contiguous memory.  A workgroup owns 128 rows of A and all output
+// columns: 8 waves, wave w covers rows 64 (w / 4) .. +64 and a 64-column
+// group; the two waves sharing a SIMD (w, w + 4) get the lightest and the
+// heaviest share of the triangle.  The reduction walks 16-column chunks of A
+// and 16-row chunks of U, both copied straight from global memory into a
+// ring of three LDS buffers (two chunks in flight while one is multiplied);
+// each wave waits for its own copies by count, then a barrier publishes them.
+// A wave skips the column groups a chunk cannot reach (U(k, j) = 0, k > j).
+//
+// FP64 arithmetic: MFMA 4x4x4 with lane l holding A(r0 + (l&15), k + (l>>4))
+// and U(k + (l>>4), c0 + (l&3)); output lane l is Q(r0 + 4((l>>2)&3) + (l>>4),
+// c0 + (l&3)).  FP32 arithmetic (F32MATH): MFMA 16x16x4 f32 on Qᵀ = Uᵀ Aᵀ,
+// first operand U(k, j0 + l%16), second A(i0 + l%16, k), result entry r of
+// lane l is Q(i0 + l%16, j0 + 4(l/16) + r).
+// A is FP64 or FP32 (TA), kept in LDS as TA and converted when read.
+// ============================================================================
+constexpr int kTallRows = 128;
+constexpr int kTallK = 16;
+constexpr int kTallUld = 256;
+constexpr int kTallBufs = 3;
+
+__device__ __forceinline__ int tall_wave_col0(int w) {
+  const int g = w & 3;
+  return 64 * ((w < 4) ? g : 3 - g);
+}
+
+// Workgroup barrier that waits only for this wave's LDS operations (not for
+// its outstanding global->LDS copies, which are waited for by count), and that
+// the compiler does not move memory accesses across.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// s_waitcnt with only the vector-memory counter limited to n (n < 16).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 16, "vmcnt field");
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8));
+}
+
+template <typename TA, bool F32MATH>
+__global__ __launch_bounds__(512, 1) void k_tall(const TA* __restrict__ A, int64_t m, int n, int64_t lda,
+                                                 const double* __restrict__ U, void* __restrict__ Qv, int64_t ldq,
+                                                 const int32_t* __restrict__ info) {
+  constexpr int kABytes = kTallK * kTallRows * (int)sizeof(TA);
+  constexpr int kUBytes = kTallK * kTallUld * 8;
+  constexpr int kBufBytes = kABytes + kUBytes;
+  // per wave and chunk: A columns of 1 KB (2 per wave) or 2 FP32 columns per KB (1 per wave); U rows 2 KB (4 per wave)
+  constexpr int kAInstr = sizeof(TA) == 8 ? 2 : 1;
+  constexpr int kUInstr = 4;
+  constexpr int kPerChunk = kAInstr + kUInstr;
+  __shared__ __attribute__((aligned(16))) char smem[kTallBufs * kBufBytes];
+  if (info != nullptr && *info != 0) return;
+  const int64_t i0 = (int64_t)blockIdx.x * kTallRows;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wr = 64 * (wave >> 2), wc = tall_wave_col0(wave);
+  const int nchunks = (n + kTallK - 1) / kTallK;
+  const bool direct = (i0 + kTallRows <= m) && (((uintptr_t)A & 15u) == 0) &&
+                      (((lda * (int64_t)sizeof(TA)) & 15) == 0);
+
+  auto abuf = [&](int b) { return (TA*)(smem + b * kBufBytes); };
+  auto ubuf = [&](int b) { return (double*)(smem + b * kBufBytes + kABytes); };
+
+  // Columns of a chunk past n are read from column n - 1 (finite data times
+  // the zero rows of U), which keeps every wave's copy count per chunk fixed.
+  auto issue = [&](int ch) {
+    const int b = ch % kTallBufs;
+    const int k0 = ch * kTallK;
+    TA* As = abuf(b);
+    if (direct) {
+      if constexpr (sizeof(TA) == 8) {
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          const int kc = 2 * wave + t;  // one column: 128 rows, lane i -> rows 2i, 2i+1
+          const int col = k0 + kc < n ? k0 + kc : n - 1;
+          __builtin_amdgcn_global_load_lds((const void*)(A + i0 + 2 * lane + (int64_t)col * lda),
+                                           (__attribute__((address_space(3))) void*)(As + kc * kTallRows), 16, 0,
+                                           0);
+        }
+      } else {
+        const int kc = 2 * wave + (lane >> 5);  // two columns: lane i -> rows 4(i&31) .. +3
+        const int col = k0 + kc < n ? k0 + kc : n - 1;
+        __builtin_amdgcn_global_load_lds((const void*)(A + i0 + 4 * (lane & 31) + (int64_t)col * lda),
+                                         (__attribute__((address_space(3))) void*)(As + 2 * wave * kTallRows), 16,
+                                         0, 0);
+      }
+    } else {
+      for (int e = tid; e < kTallK * kTallRows; e += 512) {
+        const int r = e % kTallRows, kc = e / kTallRows;
+        const int64_t gi = i0 + r;
+        const int col = k0 + kc < n ? k0 + kc : n - 1;
+        As[kc * kTallRows + r] = gi < m ? A[gi + (int64_t)col * lda] : (TA)0;
+      }
+    }
+    double* Us = ubuf(b);
+#pragma unroll
+    for (int t = 0; t < kUInstr; ++t) {
+      const int h = 4 * wave + t;  // half-row h/2 of the chunk, 128 doubles
+      const int kr = h >> 1, c0 = 128 * (h & 1);
+      __builtin_amdgcn_global_load_lds((const void*)(U + (int64_t)(k0 + kr) * kTallUld + c0 + 2 * lane),
+                                       (__attribute__((address_space(3))) void*)(Us + kr * kTallUld + c0), 16, 0, 0);
+    }
+  };
+
+  // zero the buffers once (a ragged tile's rows past m are then never garbage)
+  for (int e = tid; e < kTallBufs * kBufBytes / 8; e += 512) ((double*)smem)[e] = 0.0;
+  lds_barrier();
+
+  if constexpr (!F32MATH) {
+    double acc[4][16];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 16; ++b) acc[a][b] = 0.0;
+    issue(0);
+    if (nchunks > 1) issue(1);
+    const int ar = lane & 15, ak = lane >> 4, bc = lane & 3;
+    for (int ch = 0; ch < nchunks; ++ch) {
+      if (direct && ch + 1 < nchunks) wait_vmcnt<kPerChunk>();
+      else wait_vmcnt<0>();
+      lds_barrier();
+      if (ch + 2 < nchunks) issue(ch + 2);
+      const TA* As = abuf(ch % kTallBufs);
+      const double* Us = ubuf(ch % kTallBufs);
+      const int k0 = ch * kTallK;
+      if (wc + 63 >= k0 && wc < n) {
+#pragma unroll
+        for (int ks = 0; ks < kTallK; ks += 4) {
+          const int kk = ks + ak;
+          double a[4];
+#pragma unroll
+          for (int rt = 0; rt < 4; ++rt) a[rt] = (double)As[kk * kTallRows + wr + 16 * rt + ar];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {  // 16 columns at a time: U(k, j) = 0 for every k > j
+            if (wc + 16 * q + 15 >= k0 + ks) {
+              double b[4];
+#pragma unroll
+              for (int c = 0; c < 4; ++c) b[c] = Us[kk * kTallUld + wc + 16 * q + 4 * c + bc];
+#pragma unroll
+              for (int c = 0; c < 4; ++c)
+#pragma unroll
+                for (int rt = 0; rt < 4; ++rt)
+                  acc[rt][4 * q + c] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[rt], b[c], acc[rt][4 * q + c], 0, 0, 0);
+            }
+          }
+        }
+      }
+    }
+    double* Q = (double*)Qv;
+    const int orow = 4 * ((lane >> 2) & 3) + (lane >> 4), ocol = lane & 3;
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) {
+      const int64_t i = i0 + wr + 16 * rt + orow;
+      if (i >= m) continue;
+#pragma unroll
+      for (int cg = 0; cg < 16; ++cg) {
+        const int j = wc + 4 * cg + ocol;
+        if (j < n) Q[i + (int64_t)j * ldq] = acc[rt][cg];
+      }
+    }
+  } else {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    f4 acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+    issue(0);
+    if (nchunks > 1) issue(1);
+    const int l16 = lane & 15, k4 = lane >> 4;
+    for (int ch = 0; ch < nchunks; ++ch) {
+      if (direct && ch + 1 < nchunks) wait_vmcnt<kPerChunk>();
+      else wait_vmcnt<0>();
+      lds_barrier();
+      if (ch + 2 < nchunks) issue(ch + 2);
+      const TA* As = abuf(ch % kTallBufs);
+      const double* Us = ubuf(ch % kTallBufs);
+      const int k0 = ch * kTallK;
+      if (wc + 63 >= k0 && wc < n) {
+#pragma unroll
+        for (int ks = 0; ks < kTallK; ks += 4) {
+          const int kk = ks + k4;
+          float a[4], u[4];
+#pragma unroll
+          for (int rt = 0; rt < 4; ++rt) a[rt] = (float)As[kk * kTallRows + wr + 16 * rt + l16];
+#pragma unroll
+          for (int ct = 0; ct < 4; ++ct) u[ct] = (float)Us[kk * kTallUld + wc + 16 * ct + l16];
+#pragma unroll
+          for (int ct = 0; ct < 4; ++ct) {
+            if (wc + 16 * ct + 15 >= k0 + ks) {
+#pragma unroll
+              for (int rt = 0; rt < 4; ++rt)
+                acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(u[ct], a[rt], acc[rt][ct], 0, 0, 0);
+            }
+          }
+        }
+      }
+    }
+    float* Q = (float*)Qv;
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) {
+      const int64_t i = i0 + wr + 16 * rt + l16;
+      if (i >= m) continue;
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int j = wc + 16 * ct + 4 * k4 + r;
+          if (j < n) Q[i + (int64_t)j * ldq] = acc[rt][ct][r];
+        }
+    }
+  }
+}
+
+// Row-major, zero-padded 256 x 256 image of the upper triangle of an n x n
+// column-major X (ldx): T[256 k + j] = X(k, j) for k <= j < n, else 0.
+__global__ __launch_bounds__(256) void k_upper_image(const double* __restrict__ X, int64_t ldx, int n,
+                                                     double* __restrict__ T) {
+  __shared__ double tile[32][33];
+  const int bk = blockIdx.y * 32, bj = blockIdx.x * 32;  // T rows k, columns j
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int q = ty; q < 32; q += 8) {  // read X(k = bk + tx, j = bj + q): coalesced along k
+    const int k = bk + tx, j = bj + q;
+    tile[q][tx] = (k <= j && j < n) ? X[k + (int64_t)j * ldx] : 0.0;
+  }
+  __syncthreads();
+  for (int q = ty; q < 32; q += 8) {  // write T[k = bk + q][j = bj + tx]: coalesced along j
+    T[(int64_t)(bk + q) * kTallUld + bj + tx] = tile[tx][q];
+  }
+}
+
+hipError_t launch_upper_image(const double* X, int64_t ldx, int n, double* T, hipStream_t s) {
+  if (n > kTallUld) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_upper_image, dim3(kTallUld / 32, kTallUld / 32), dim3(256), 0, s, X, ldx, n, T);
+  return hipGetLastError();
+}
+
+hipError_t launch_tall_gemm(int a_f32, const void* A, int64_t m, int n, int64_t lda, const double* Uimg, double* Q,
+                            int64_t ldq, const int32_t* info, hipStream_t s) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  if (n > kTallUld) return hipErrorInvalidValue;
+  dim3 grid((unsigned)((m + kTallRows - 1) / kTallRows));
+  if (a_f32)
+    hipLaunchKernelGGL((k_tall<float, false>), grid, dim3(512), 0, s, (const float*)A, m, n, lda, Uimg, (void*)Q,
+                       ldq, info);
+  else
+    hipLaunchKernelGGL((k_tall<double, false>), grid, dim3(512), 0, s, (const double*)A, m, n, lda, Uimg, (void*)Q,
+                       ldq, info);
+  return hipGetLastError();
+}
+
+hipError_t launch_tall_gemm_f32(const double* A, int64_t m, int n, int64_t lda, const double* Uimg, float* Q,
+                                int64_t ldq, const int32_t* info, hipStream_t s) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  if (n > kTallUld) return hipErrorInvalidValue;
+  dim3 grid((unsigned)((m + kTallRows - 1) / kTallRows));
+  hipLaunchKernelGGL((k_tall<double, true>), grid, dim3(512), 0, s, A, m, n, lda, Uimg, (void*)Q, ldq, info);
+  return hipGetLastError();
+}
+
+}  // namespace cqr2
