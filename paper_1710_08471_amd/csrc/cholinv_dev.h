@@ -17,9 +17,9 @@ namespace cqr2 {
 // The n x n register-resident matrix M holds W' / L in its lower triangle and
 // Zᵀ / Yᵀ (= R^{-1}) in its strict upper triangle; thread (r, c) of a G x G
 // grid owns M(r + G a, c + G b) (a cyclic distribution, so the shrinking
-// trailing matrix stays spread over all threads).  One barrier per column:
-// the owners of column j publish it to a double-buffered LDS vector, every
-// thread forms L(:,j) and Y(j,:) from it and applies the rank-1 updates.
+// trailing matrix stays spread over all threads).  The owners of a block of
+// columns publish them to a double-buffered LDS panel, every thread forms the
+// L and Y entries it needs from it and applies the rank-B updates.
 // ============================================================================
 // Input of the factorization: the lower triangle of W (n x n, ldw), or -- when
 // `part` is set -- the sum, in split order, of `splits` partial Grams laid
@@ -43,15 +43,28 @@ __device__ __forceinline__ double cholinv_src(const CholInvSrc& s, int p, int q)
   return v;
 }
 
+// Blocked form: B columns per barrier.  The owners of columns j0 .. j0+B-1
+// publish them; every thread factors the B x B diagonal block itself (the
+// same operations in the same order, so every thread gets the same bits),
+// forms for each of its rows p the vector v(p) of L(p, j) (p below the block)
+// or Y(j, p) (p above or inside it), and for each of its columns q the vector
+// L(q, j), j in the block, and applies one rank-B update: the Schur update
+// M(p, q) -= sum_j L(p, j) L(q, j) below the diagonal and the inverse's update
+// Z(q, p) -= sum_j L(q, j) Y(j, p) above it (Y(j, p) = 0 for rows p below
+// the block).
+// B = 1 is the column-by-column form.
+//
 // Threads tid < G*G do the work; any further threads of the workgroup run
 // the same loop as shadows (same barriers, no stores) so the body can sit in
-// a workgroup larger than the grid.  colbuf: 2 * G * T doubles of LDS.
-template <int T, int G>
+// a workgroup larger than the grid.  colbuf: 2 * B * G * T doubles of LDS.
+template <int T, int G, int B>
 __device__ __forceinline__ void cholinv_body(const CholInvSrc& src, int n, double* __restrict__ R, int64_t ldr,
                                              double* __restrict__ Rinv, int64_t ldri, double* __restrict__ Upad,
                                              int np, int32_t* __restrict__ info, int info_offset, double* colbuf_) {
   constexpr int NP = G * T;
-  double (*colbuf)[NP] = reinterpret_cast<double (*)[NP]>(colbuf_);
+  static_assert(G % B == 0, "a block of columns must not straddle two column blocks of the grid");
+  // colbuf[buffer][k][idx]: column j0 + k of the block, row p stored at idx (p % G) T + p / G
+  double (*colbuf)[B][NP] = reinterpret_cast<double (*)[B][NP]>(colbuf_);
   const int tid = threadIdx.x;
   const bool worker = tid < G * G;
   const int r = (tid % (G * G)) / G, c = tid % G;
@@ -70,58 +83,128 @@ __device__ __forceinline__ void cholinv_body(const CholInvSrc& src, int n, doubl
     }
 
   if (fail == 0) {
+    int step = 0;
 #pragma unroll
     for (int jb = 0; jb < T; ++jb) {
       if (G * jb >= n || fail != 0) break;
-      for (int jc = 0; jc < G; ++jc) {
-        const int j = G * jb + jc;
-        if (j >= n) break;
-        double* buf = colbuf[j & 1];
-        if (worker && c == jc) {
+      for (int jc0 = 0; jc0 < G; jc0 += B) {
+        const int j0 = G * jb + jc0;
+        if (j0 >= n) break;
+        double (*buf)[NP] = colbuf[step & 1];
+        ++step;
+        if (worker && c >= jc0 && c < jc0 + B) {
 #pragma unroll
-          for (int a = 0; a < T; ++a) buf[r * T + a] = M[a][jb];
+          for (int a = 0; a < T; ++a) buf[c - jc0][r * T + a] = M[a][jb];
         }
         __syncthreads();
-        const double d = buf[jc * T + jb];
-        if (!(d > 0.0)) {  // non-positive or NaN pivot (uniform across the workgroup)
-          fail = j + 1;
+        // the diagonal block, factored by every thread: Lb lower with L(j,j) on
+        // the diagonal, Yb(k, i) = Y(j0 + k, j0 + i) for i <= k
+        double D[B][B], Lb[B][B], Yb[B][B], sd[B], y[B];
+#pragma unroll
+        for (int i = 0; i < B; ++i)
+#pragma unroll
+          for (int k = 0; k < B; ++k) {
+            const int p = j0 + i;
+            D[i][k] = buf[k][(p % G) * T + p / G];
+          }
+        int bad = 0;
+#pragma unroll
+        for (int jj = 0; jj < B; ++jj) {
+          double d = D[jj][jj];
+#pragma unroll
+          for (int ii = 0; ii < jj; ++ii) d = fma(-Lb[jj][ii], Lb[jj][ii], d);
+          if (!(d > 0.0) && bad == 0) bad = j0 + jj + 1;  // non-positive or NaN pivot (uniform)
+          sd[jj] = sqrt(d);
+          y[jj] = 1.0 / sd[jj];
+          Lb[jj][jj] = sd[jj];
+#pragma unroll
+          for (int kk = jj + 1; kk < B; ++kk) {
+            double t = D[kk][jj];
+#pragma unroll
+            for (int ii = 0; ii < jj; ++ii) t = fma(-Lb[kk][ii], Lb[jj][ii], t);
+            Lb[kk][jj] = t * y[jj];
+          }
+          Yb[jj][jj] = y[jj];
+#pragma unroll
+          for (int pp = 0; pp < jj; ++pp) {
+            double t = D[pp][jj];  // upper entry: Z(j0 + jj, j0 + pp)
+#pragma unroll
+            for (int ii = pp; ii < jj; ++ii) t = fma(-Lb[jj][ii], Yb[ii][pp], t);
+            Yb[jj][pp] = t * y[jj];
+          }
+        }
+        if (bad != 0) {
+          fail = bad;
           break;
         }
-        const double sd = sqrt(d);
-        const double y = 1.0 / sd;
-        double lvp[T], yvp[T], lvq[T];
+        // rows: v(p); the same recurrence gives L(p, j) below the block and
+        // Y(j, p) above it; rows inside the block take Yb
+        double v[T][B];
 #pragma unroll
         for (int a = 0; a < T; ++a) {
           const int p = r + G * a;
-          const double v = buf[r * T + a];
-          lvp[a] = (p > j) ? v * y : 0.0;
-          yvp[a] = (p < j) ? v * y : (p == j ? y : 0.0);
-        }
 #pragma unroll
-        for (int b = 0; b < T; ++b) {
-          const int q = c + G * b;
-          lvq[b] = (q > j) ? buf[c * T + b] * y : 0.0;
-        }
-        if (c == jc) {
+          for (int jj = 0; jj < B; ++jj) {
+            double t = buf[jj][r * T + a];
 #pragma unroll
-          for (int a = 0; a < T; ++a) {
-            const int p = r + G * a;
-            M[a][jb] = (p > j) ? lvp[a] : (p == j ? sd : yvp[a]);
+            for (int ii = 0; ii < jj; ++ii) t = fma(-Lb[jj][ii], v[a][ii], t);
+            v[a][jj] = t * y[jj];
           }
+          const int pp = p - j0;  // register arrays take compile-time indices only
+#pragma unroll
+          for (int i = 0; i < B; ++i)
+            if (pp == i) {
+#pragma unroll
+              for (int jj = 0; jj < B; ++jj) v[a][jj] = jj >= i ? Yb[jj][i] : 0.0;
+            }
         }
-        const bool low_diag = r >= c;  // element (a,a) of this thread is in the lower triangle
+        // columns right of the block: L(q, j)
+        double lq[T][B];
 #pragma unroll
         for (int b = jb; b < T; ++b) {
 #pragma unroll
+          for (int jj = 0; jj < B; ++jj) {
+            double t = buf[jj][c * T + b];
+#pragma unroll
+            for (int ii = 0; ii < jj; ++ii) t = fma(-Lb[jj][ii], lq[b][ii], t);
+            lq[b][jj] = t * y[jj];
+          }
+        }
+        // owners finalize the block's columns
+#pragma unroll
+        for (int kk = 0; kk < B; ++kk) {
+          if (c != jc0 + kk) continue;
+#pragma unroll
           for (int a = 0; a < T; ++a) {
-            if (a > b) {
-              M[a][b] = fma(-lvp[a], lvq[b], M[a][b]);
-            } else if (a < b) {
-              if (a <= jb) M[a][b] = fma(-yvp[a], lvq[b], M[a][b]);
-            } else {
-              const double f = low_diag ? lvp[a] : yvp[a];
-              M[a][b] = fma(-f, lvq[b], M[a][b]);
+            const int pp = r + G * a - j0;
+            double val = v[a][kk];  // L(p, j) below the block, Y(j, p) above it
+#pragma unroll
+            for (int i = 0; i < B; ++i)
+              if (pp == i) val = i > kk ? Lb[i][kk] : (i == kk ? sd[kk] : Yb[kk][i]);
+            M[a][jb] = val;
+          }
+        }
+        // rank-B update of every element right of the block: below the
+        // diagonal with v(p) = L(p, .), above it with Y(., p), which is v(p)
+        // for rows above or inside the block and zero for rows below it
+        const bool right_of_block = c >= jc0 + B;  // column c + G jb lies right of the block
+        const bool low_diag = r >= c;              // element (a, a) of this thread lies on or below the diagonal
+#pragma unroll
+        for (int a = 0; a < T; ++a) {
+          const bool row_up = r + G * a < j0 + B;
+          double vu[B];
+#pragma unroll
+          for (int jj = 0; jj < B; ++jj) vu[jj] = row_up ? v[a][jj] : 0.0;
+#pragma unroll
+          for (int b = jb; b < T; ++b) {
+            if (b == jb && !right_of_block) continue;
+            double t = M[a][b];
+#pragma unroll
+            for (int jj = 0; jj < B; ++jj) {
+              const double f = a > b ? v[a][jj] : (a < b ? vu[jj] : (low_diag ? v[a][jj] : vu[jj]));
+              t = fma(-f, lq[b][jj], t);
             }
+            M[a][b] = t;
           }
         }
       }

@@ -10,14 +10,20 @@
 
 namespace cqr2 {
 
+// Columns per barrier of the one-problem kernel: 4, or 2 at the largest
+// tile (T = 8), where a wider block would not fit the register file.
+template <int T>
+constexpr int cholinv_block() { return T >= 8 ? 2 : 4; }
+
 template <int T, int G>
 __global__ __launch_bounds__(G * G) void k_cholinv(const double* __restrict__ W, int64_t ldw, int n,
                                                  double* __restrict__ R, int64_t ldr, double* __restrict__ Rinv,
                                                  int64_t ldri, double* __restrict__ Upad, int np,
                                                  int32_t* __restrict__ info, int info_offset) {
-  __shared__ double colbuf[2 * G * T];
+  constexpr int B = cholinv_block<T>();
+  __shared__ double colbuf[2 * B * G * T];
   const CholInvSrc src{W, ldw, nullptr, 0, 0};
-  cholinv_body<T, G>(src, n, R, ldr, Rinv, ldri, Upad, np, info, info_offset, colbuf);
+  cholinv_body<T, G, B>(src, n, R, ldr, Rinv, ldri, Upad, np, info, info_offset, colbuf);
 }
 
 int padded_order(int64_t n) {
@@ -26,20 +32,18 @@ int padded_order(int64_t n) {
   return 128;
 }
 
-// Thread grid of the one-workgroup CholInv: G x G threads, each owning a
-// T x T cyclic tile of the padded order G T.  Up to n = 64 a 16 x 16 grid has
-// the shorter per-column critical path; above, 32 x 32 threads share the
-// larger Schur updates.
+// Thread grid of the one-workgroup CholInv: 16 x 16 threads, each owning a
+// T x T cyclic tile of the padded order 16 T (T = 2, 4, 8).
 hipError_t launch_cholinv(const double* W, int64_t ldw, int n, double* R, int64_t ldr, double* Rinv,
                           int64_t ldri, double* Upad, int np, int32_t* info, int info_offset,
                           hipStream_t s) {
   const int order = padded_order(n);
-#define CQR2_CI(TV, GV)                                                                                         \
-  hipLaunchKernelGGL((k_cholinv<TV, GV>), dim3(1), dim3(GV * GV), 0, s, W, ldw, n, R, ldr, Rinv, ldri, Upad, np, \
-                     info, info_offset)
-  if (order == 32) CQR2_CI(2, 16);
-  else if (order == 64) CQR2_CI(4, 16);
-  else if (order == 128) CQR2_CI(4, 32);
+#define CQR2_CI(TV)                                                                                           \
+  hipLaunchKernelGGL((k_cholinv<TV, 16>), dim3(1), dim3(256), 0, s, W, ldw, n, R, ldr, Rinv, ldri, Upad, np, info, \
+                     info_offset)
+  if (order == 32) CQR2_CI(2);
+  else if (order == 64) CQR2_CI(4);
+  else if (order == 128) CQR2_CI(8);
   else return hipErrorInvalidValue;
 #undef CQR2_CI
   return hipGetLastError();

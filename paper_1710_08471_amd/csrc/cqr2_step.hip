@@ -101,7 +101,7 @@ __device__ __forceinline__ void step_run(const StepTask& t, int sub, double* lds
     case 4: {
       const CholInvSrc src{nullptr, 0, part, splits, NBLK};
       const bool p1 = t.phase == 1;
-      cholinv_body<NP / 16, 16>(src, n, p1 ? R1 : R2, n, nullptr, 0, p1 ? U1 : U2, NP, info, p1 ? 0 : n, lds);
+      cholinv_body<NP / 16, 16, 2>(src, n, p1 ? R1 : R2, n, nullptr, 0, p1 ? U1 : U2, NP, info, p1 ? 0 : n, lds);
       break;
     }
     case 2:

@@ -14,6 +14,8 @@
 #include <cmath>
 #include <cstdint>
 
+#include "sync_dev.h"
+
 namespace cqr2 {
 
 // ============================================================================
@@ -257,18 +259,6 @@ constexpr int kTallBufs = 3;
 __device__ __forceinline__ int tall_wave_col0(int w) {
   const int g = w & 3;
   return 64 * ((w < 4) ? g : 3 - g);
-}
-
-// Workgroup barrier that waits only for this wave's LDS operations (not for
-// its outstanding global->LDS copies, which are waited for by count), and that
-// the compiler does not move memory accesses across.
-__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
-
-// s_waitcnt with only the vector-memory counter limited to n (n < 16).
-template <int N>
-__device__ __forceinline__ void wait_vmcnt() {
-  static_assert(N >= 0 && N < 16, "vmcnt field");
-  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8));
 }
 
 template <typename TA, bool F32MATH>
