@@ -5,8 +5,6 @@
 #include <cmath>
 #include <cstdint>
 
-#include "sync_dev.h"
-
 namespace cqr2 {
 // ============================================================================
 // Q = A U with U upper triangular (NT x NT padded, NT = 32, 64 or 128), FP64
@@ -188,12 +186,6 @@ __device__ __forceinline__ void apply_wave_run(const double* A, int64_t m, int n
   const int orow = 4 * ((lane >> 2) & 3) + (lane >> 4);
   const int ocol = lane & 3;
   double acc[kApplyTiles][JPW];
-  // A stage's stores: one instruction per (row tile, column group) whose
-  // columns reach below n; every row of a full stage is below m.
-  int groups_below_n = 0;
-#pragma unroll
-  for (int t = 0; t < JPW; ++t) groups_below_n += (4 * L::group(W, t) < n) ? 1 : 0;
-  const int stores_per_stage = kApplyTiles * groups_below_n;
   auto store = [&](int64_t sidx) {
 #pragma unroll
     for (int rt = 0; rt < kApplyTiles; ++rt) {
@@ -210,20 +202,16 @@ __device__ __forceinline__ void apply_wave_run(const double* A, int64_t m, int n
   int cur = 0;
   int64_t prev = -1;
   for (; st < s_end; st += s_stride) {
-    // copies of the next stage first, then the previous stage's stores: the
-    // wait below covers the copies and leaves the stores in flight
+    if (prev >= 0) store(prev);
     const int64_t nxt = st + s_stride;
     if (nxt < s_end) fill(nxt, sa + (cur ^ 1) * kBuf);
-    const bool counted = prev >= 0 && (prev + 1) * kApplyRows <= m;
-    if (prev >= 0) store(prev);
 #pragma unroll
     for (int rt = 0; rt < kApplyTiles; ++rt)
 #pragma unroll
       for (int t = 0; t < JPW; ++t) acc[rt][t] = 0.0;
     AW::stage(sa + cur * kBuf, lane, u, acc);
-    if (counted) wait_vmcnt_dyn(stores_per_stage);
-    else wait_vmcnt<0>();
-    lds_barrier();
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
     cur ^= 1;
     prev = st;
   }
