@@ -10,6 +10,8 @@ from .cqr2_ref import (  # noqa: F401
     cqr,
     cqr2,
     cqr2_mixed,
+    cholesky_shift,
+    scqr3,
     syrk,
     upper_product,
 )

@@ -24,6 +24,15 @@ itself prescribes.  Readings where the paper is silent:
   not by a triangular solve.
 * The second pass factors the stored Q1 (in the mixed form: the FP32 values,
   converted exactly to FP64).
+
+Shifted CholeskyQR3 (``scqr3``): the paper names the shifted variant of
+Fukaya et al. (its Conclusion and the CholeskyQR2 background of its
+Introduction) as an unconditionally stable extension that needs only minimal
+changes, without defining it.  It is written here from that published method:
+one CholeskyQR of A with W + s I in place of W, s = 11 (m n + n (n + 1)) u
+||A||_F^2 (u = 2^-53, ||A||_F^2 = trace W), followed by CholeskyQR2 of the
+result; R = R3 R2 R1.  Parity of this form is pinned to Householder QR, closed
+forms and exact scaling, not to anything the paper prints.
 """
 from __future__ import annotations
 
@@ -164,3 +173,38 @@ def cqr2_mixed(a: np.ndarray, return_intermediates: bool = False):
         return q, r
     return q, r, {"W1": w1, "R1": r1, "R1inv": r1inv, "Q1": q1,
                   "R2": r2, "R2inv": r2inv}
+
+
+UNIT_ROUNDOFF = 2.0 ** -53
+
+
+def cholesky_shift(w: np.ndarray, m: int) -> float:
+    """Shift s = 11 (m n + n (n + 1)) u trace(W) of shifted CholeskyQR (trace W = ||A||_F^2)."""
+    n = w.shape[0]
+    return 11.0 * (m * n + n * (n + 1)) * UNIT_ROUNDOFF * float(np.trace(w))
+
+
+def scqr3(a: np.ndarray, return_intermediates: bool = False):
+    """[Q, R] = shifted CholeskyQR3: CQR with a shifted Gram, then CQR2.
+
+    Breakdowns report the column of the pass: j, n + j or 2 n + j.
+    """
+    a = np.asarray(a, dtype=np.float64)
+    m, n = a.shape
+    w = syrk(a)
+    s = cholesky_shift(w, m)
+    l1, y1 = cholinv(w + s * np.eye(n))
+    r1 = l1.T.copy()
+    q1 = a @ y1.T
+    try:
+        q2, r2, _ = cqr(q1)
+    except NotSPD as e:
+        raise NotSPD(n + e.j) from None
+    try:
+        q, r3, _ = cqr(q2)
+    except NotSPD as e:
+        raise NotSPD(2 * n + e.j) from None
+    r = upper_product(r3, upper_product(r2, r1))
+    if not return_intermediates:
+        return q, r
+    return q, r, {"shift": s, "R1": r1, "Q1": q1, "R2": r2, "R3": r3}

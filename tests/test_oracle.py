@@ -289,3 +289,61 @@ def test_pins_catch_planted_second_pass_skip(monkeypatch):
     a = gdv_matrix(2000, 32, 1e6, 2)
     q1, r1, _ = oracle.cqr(a)
     assert oracle.orthogonality(q1) > 1e-12
+
+
+# ---- shifted CholeskyQR3 (the unconditionally stable extension the paper cites) ----
+
+@pytest.mark.parametrize("kappa", [1e10, 1e12, 1e14])
+def test_scqr3_householder_accuracy_where_cqr2_breaks_down(kappa):
+    """Past cond ~ u^(-1/2) the Gram matrix is numerically singular: CQR2's
+    Cholesky fails, the shifted form stays as accurate as Householder QR."""
+    a = gdv_matrix(3000, 40, kappa, 301)
+    with pytest.raises(oracle.NotSPD):
+        oracle.cqr2(a)
+    q, r = oracle.scqr3(a)
+    assert np.array_equal(r, np.triu(r)) and np.all(np.diag(r) > 0)
+    assert oracle.orthogonality(q) <= 1e-13
+    assert oracle.residual(a, q, r) <= 1e-14
+    rh = oracle.householder_qr_posdiag(a)[1]
+    assert oracle.rel_fro(r, rh) <= 1e-12
+
+
+@pytest.mark.parametrize("m,n,kappa,seed", [(2000, 30, 1e3, 302), (5000, 64, 1e6, 303)])
+def test_scqr3_agrees_with_cqr2_in_its_range(m, n, kappa, seed):
+    a = gdv_matrix(m, n, kappa, seed)
+    q2, r2 = oracle.cqr2(a)
+    q3, r3 = oracle.scqr3(a)
+    assert oracle.rel_fro(r3, r2) <= 1e-12
+    assert np.max(np.abs(q3 - q2)) <= 1e-9
+
+
+def test_scqr3_orthonormal_columns_closed_form():
+    """A with orthonormal columns: W = I, so R1 = sqrt(1 + s) I and the two
+    refinement passes undo the scaling: R = I and Q = A up to a few ulps."""
+    h = scipy.linalg.hadamard(256)[:, :24] / 16.0
+    q, r = oracle.scqr3(h)
+    assert np.max(np.abs(r - np.eye(24))) <= 8 * 2.0 ** -52
+    assert np.max(np.abs(q - h)) <= 8 * 2.0 ** -52
+
+
+def test_scqr3_shift_scales_with_the_gram():
+    a = gdv_matrix(500, 10, 1e2, 304)
+    w = oracle.syrk(a)
+    s = oracle.cholesky_shift(w, 500)
+    assert s > 0.0
+    assert oracle.cholesky_shift(w * 4.0, 500) == 4.0 * s   # exact: trace and s scale by powers of two
+
+
+def test_scqr3_power_of_two_scaling_is_exact():
+    a = gdv_matrix(1000, 20, 1e12, 305)
+    q1, r1 = oracle.scqr3(a)
+    q2, r2 = oracle.scqr3(a * 2.0 ** 20)
+    assert np.array_equal(q1, q2)
+    assert np.array_equal(r1 * 2.0 ** 20, r2)
+
+
+def test_scqr3_pins_catch_a_missing_shift(monkeypatch):
+    monkeypatch.setattr(cqr2_ref, "cholesky_shift", lambda w, m: 0.0)
+    a = gdv_matrix(3000, 40, 1e12, 301)
+    with pytest.raises(oracle.NotSPD):
+        cqr2_ref.scqr3(a)
