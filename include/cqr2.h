@@ -55,6 +55,15 @@ extern "C" {
  * Accepted by cqr2_factor_ex / cqr2_workspace_size. */
 #define CQR2_MIXED_P1_FP32 1u
 
+/* Shifted CholeskyQR3, the unconditionally stable extension of CholeskyQR2
+ * the paper cites (Fukaya et al.): the first CholeskyQR factors W + s I,
+ * s = 11 (m n + n (n + 1)) 2^-53 trace(W) (trace W = ||A||_F^2), then
+ * CholeskyQR2 of its Q; R = R3 R2 R1.  Stays as accurate as Householder QR far
+ * past cond(A) ~ 1e8, where CholeskyQR2's Cholesky breaks down; costs one
+ * more pass.  FP64.  Breakdown codes j, n + j, 2 n + j for the three passes.
+ * Accepted by cqr2_factor_ex / cqr2_workspace_size. */
+#define CQR2_SHIFTED_CQR3 2u
+
 /* Largest n accepted (every n x n workspace block is n*n*8 bytes).  Up to
  * n = 128 the tall-skinny kernels run (split-K Gram, one-workgroup CholInv,
  * streaming Q = A R^{-1}); above, the Gram, Q formation and R2 R1 are tiled

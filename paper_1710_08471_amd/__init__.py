@@ -21,6 +21,7 @@ CQR2_ERR_UNSUPPORTED = -101
 CQR2_ERR_TOO_LARGE = -102
 CQR2_FP64 = 0
 CQR2_MIXED_P1_FP32 = 1
+CQR2_SHIFTED_CQR3 = 2
 NUM_TIMERS = 6
 TIMER_NAMES = ("gram", "gram_reduce", "cholinv", "apply_rinv_pass1", "apply_rinv_pass2", "upper_product")
 

@@ -71,7 +71,13 @@ SmallLayout make_small_layout(int64_t m, int64_t n) {
 
 // FP64 factorizations with n <= 128 run the tall-skinny kernels; everything
 // else (n > 128, and the mixed-precision form at any n) runs the tiled path.
-bool use_small(int64_t n, uint32_t flags) { return n <= kSmallN && flags == CQR2_FP64; }
+bool use_small(int64_t n, uint32_t flags) {
+  return n <= kSmallN && (flags == CQR2_FP64 || flags == CQR2_SHIFTED_CQR3);
+}
+
+bool valid_flags(uint32_t flags) {
+  return flags == CQR2_FP64 || flags == CQR2_MIXED_P1_FP32 || flags == CQR2_SHIFTED_CQR3;
+}
 
 size_t factor_workspace(int64_t m, int64_t n, uint32_t flags) {
   return use_small(n, flags) ? make_small_layout(m, n).total
@@ -168,7 +174,7 @@ int check_hip(hipError_t e) { return e == hipSuccess ? 0 : CQR2_ERR_HIP; }
 
 // The enqueued CholeskyQR2 sequence for n <= 128; arguments already validated.
 int run_small(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, int64_t ldq, double* R, int64_t ldr,
-              char* ws, const SmallLayout& L, int32_t* d_info, hipStream_t s, int cus) {
+              char* ws, const SmallLayout& L, int32_t* d_info, hipStream_t s, int cus, bool shifted) {
   const cqr2::TimerHook th = timer_hook();
   int32_t* info = (int32_t*)(ws + L.off_info);
   double* part = (double*)(ws + L.off_part);
@@ -182,6 +188,7 @@ int run_small(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, int
   // ---- pass 1: CQR(A) ----
   th.begin(0, s); CQR2_TRY(cqr2::launch_gram_partials(L.gram, A, m, ni, lda, part, info, s)); th.end(0, s);
   th.begin(1, s); CQR2_TRY(cqr2::launch_gram_reduce(L.gram, part, ni, W, n, info, s)); th.end(1, s);
+  if (shifted) CQR2_TRY(cqr2::launch_shift_diag(W, n, n, m, info, s));
   th.begin(2, s); CQR2_TRY(cqr2::launch_cholinv(W, n, ni, R1, n, nullptr, 0, U1, L.np, info, 0, s)); th.end(2, s);
   th.begin(3, s); CQR2_TRY(cqr2::launch_apply_rinv(A, m, ni, lda, U1, L.np, 1, Q, ldq, info, cus, s)); th.end(3, s);
   // ---- pass 2: CQR(Q1), in place ----
@@ -189,10 +196,23 @@ int run_small(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, int
   th.begin(1, s); CQR2_TRY(cqr2::launch_gram_reduce(L.gram, part, ni, W, n, info, s)); th.end(1, s);
   th.begin(2, s); CQR2_TRY(cqr2::launch_cholinv(W, n, ni, R2, n, nullptr, 0, U2, L.np, info, ni, s)); th.end(2, s);
   th.begin(4, s); CQR2_TRY(cqr2::launch_apply_rinv(Q, m, ni, ldq, U2, L.np, 1, Q, ldq, info, cus, s)); th.end(4, s);
-  // ---- R = R2 R1 (W is free again) ----
+  constexpr int kUp = cqr2::GEMM_A_UPPER | cqr2::GEMM_B_UPPER | cqr2::GEMM_C_UPPER;
+  if (!shifted) {
+    // ---- R = R2 R1 (W is free again) ----
+    th.begin(5, s);
+    CQR2_TRY(cqr2::launch_gemm(0, 0, n, n, n, 1.0, R2, n, R1, n, 0.0, W, n, kUp, 1, nullptr, info, s));
+    CQR2_TRY(cqr2::launch_finalize_r(W, n, R, ldr, n, info, d_info, s));
+    th.end(5, s);
+    return 0;
+  }
+  // ---- shifted CholeskyQR3: R2 R1 held in the caller's R, a third pass on Q ----
+  CQR2_TRY(cqr2::launch_gemm(0, 0, n, n, n, 1.0, R2, n, R1, n, 0.0, R, ldr, kUp, 1, nullptr, info, s));
+  th.begin(0, s); CQR2_TRY(cqr2::launch_gram_partials(L.gram, Q, m, ni, ldq, part, info, s)); th.end(0, s);
+  th.begin(1, s); CQR2_TRY(cqr2::launch_gram_reduce(L.gram, part, ni, W, n, info, s)); th.end(1, s);
+  th.begin(2, s); CQR2_TRY(cqr2::launch_cholinv(W, n, ni, R2, n, nullptr, 0, U1, L.np, info, 2 * ni, s)); th.end(2, s);
+  th.begin(4, s); CQR2_TRY(cqr2::launch_apply_rinv(Q, m, ni, ldq, U1, L.np, 1, Q, ldq, info, cus, s)); th.end(4, s);
   th.begin(5, s);
-  CQR2_TRY(cqr2::launch_gemm(0, 0, n, n, n, 1.0, R2, n, R1, n, 0.0, W, n,
-                             cqr2::GEMM_A_UPPER | cqr2::GEMM_B_UPPER | cqr2::GEMM_C_UPPER, 1, nullptr, info, s));
+  CQR2_TRY(cqr2::launch_gemm(0, 0, n, n, n, 1.0, R2, n, R, ldr, 0.0, W, n, kUp, 1, nullptr, info, s));
   CQR2_TRY(cqr2::launch_finalize_r(W, n, R, ldr, n, info, d_info, s));
   th.end(5, s);
   return 0;
@@ -200,11 +220,13 @@ int run_small(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, int
 
 int run_factor(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, int64_t ldq, double* R, int64_t ldr,
                char* ws, int32_t* d_info, uint32_t flags, hipStream_t s) {
+  const bool shifted = flags == CQR2_SHIFTED_CQR3;
   if (use_small(n, flags))
-    return run_small(A, m, n, lda, Q, ldq, R, ldr, ws, make_small_layout(m, n), d_info, s, device_cus());
+    return run_small(A, m, n, lda, Q, ldq, R, ldr, ws, make_small_layout(m, n), d_info, s, device_cus(), shifted);
   const bool mixed = flags == CQR2_MIXED_P1_FP32;
   const cqr2::GeneralPlan p = cqr2::plan_general(m, n, mixed);
-  return check_hip(cqr2::factor_general(A, m, n, lda, Q, ldq, R, ldr, ws, p, mixed, d_info, s, timer_hook()));
+  return check_hip(
+      cqr2::factor_general(A, m, n, lda, Q, ldq, R, ldr, ws, p, mixed, d_info, s, timer_hook(), shifted));
 }
 
 }  // namespace
@@ -226,7 +248,7 @@ const char* cqr2_status_string(int code) {
 }
 
 size_t cqr2_workspace_size(int64_t m, int64_t n, uint32_t flags) {
-  if (m < n || n < 1 || (flags != CQR2_FP64 && flags != CQR2_MIXED_P1_FP32) || n > CQR2_MAX_N) return 0;
+  if (m < n || n < 1 || !valid_flags(flags) || n > CQR2_MAX_N) return 0;
   return factor_workspace(m, n, flags);
 }
 
@@ -239,7 +261,7 @@ int cqr2_factor_ex(const double* A, int64_t m, int64_t n, int64_t lda, double* Q
   if (lda < (m > 1 ? m : 1)) return -4;
   if (ldq < (m > 1 ? m : 1)) return -6;
   if (ldr < (n > 1 ? n : 1)) return -8;
-  if (flags != CQR2_FP64 && flags != CQR2_MIXED_P1_FP32) return -12;
+  if (!valid_flags(flags)) return -12;
   if (n == 0) return 0;
   if (A == nullptr || !aligned8(A)) return -1;
   if (Q == nullptr || !aligned8(Q)) return -5;

@@ -102,6 +102,32 @@ hipError_t launch_set_info(int32_t* info, int32_t value, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Shifted CholeskyQR's first pass factors W + s I with
+// s = 11 (m n + n (n + 1)) u trace(W), u = 2^-53 (trace W = ||A||_F^2).  One
+// workgroup: strided partial sums of the diagonal, then a fixed-order tree,
+// so the shift is the same bits on every run.
+__global__ __launch_bounds__(256) void k_shift_diag(double* W, int64_t ldw, int64_t n, int64_t m,
+                                                    const int32_t* info) {
+  __shared__ double part[256];
+  if (info != nullptr && *info != 0) return;
+  double t = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) t += W[i + i * ldw];
+  part[threadIdx.x] = t;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+    __syncthreads();
+  }
+  const double trace = part[0];
+  const double s = 11.0 * ((double)m * (double)n + (double)n * (double)(n + 1)) * 0x1p-53 * trace;
+  for (int64_t i = threadIdx.x; i < n; i += 256) W[i + i * ldw] += s;
+}
+
+hipError_t launch_shift_diag(double* W, int64_t ldw, int64_t n, int64_t m, const int32_t* info, hipStream_t s) {
+  hipLaunchKernelGGL(k_shift_diag, dim3(1), dim3(256), 0, s, W, ldw, n, m, info);
+  return hipGetLastError();
+}
+
 // W(j, i) = W(i, j) for i > j (complete a lower-triangle result).
 __global__ void k_mirror_lower(double* W, int64_t ldw, int64_t n) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -169,7 +195,7 @@ GeneralPlan plan_general(int64_t m, int64_t n, bool mixed) {
 
 hipError_t factor_general(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, int64_t ldq, double* R,
                           int64_t ldr, char* ws, const GeneralPlan& p, bool mixed, int32_t* d_info, hipStream_t s,
-                          const TimerHook& th) {
+                          const TimerHook& th, bool shifted) {
   int32_t* info = (int32_t*)(ws + p.off_info);
   double* W = (double*)(ws + p.off_w);
   double* R1 = (double*)(ws + p.off_r1);
@@ -193,6 +219,7 @@ hipError_t factor_general(const double* A, int64_t m, int64_t n, int64_t lda, do
     CQR2_HIP(launch_gemm(1, 0, n, n, m, 1.0, A, lda, A, lda, 0.0, W, n, GEMM_C_LOWER, p.gram_splits,
                          (double*)scratch, info, s));
   th.end(0, s);
+  if (shifted) CQR2_HIP(launch_shift_diag(W, n, n, m, info, s));
   th.begin(2, s);
   CQR2_HIP(cholinv_recursive(W, n, n, R1, n, Ri1, n, scratch, info, 0, s));
   th.end(2, s);
@@ -228,11 +255,41 @@ hipError_t factor_general(const double* A, int64_t m, int64_t n, int64_t lda, do
     CQR2_HIP(launch_gemm_in32(q1f, 0, 0, 0, m, n, n, 1.0, Q1, m, Ri2, n, 0.0, Q, ldq, GEMM_B_UPPER, 1, nullptr,
                               info, s));
   th.end(4, s);
-  // R = R2 R1
+  constexpr int kUp = GEMM_A_UPPER | GEMM_B_UPPER | GEMM_C_UPPER;
+  if (!shifted) {
+    // R = R2 R1
+    th.begin(5, s);
+    CQR2_HIP(launch_gemm(0, 0, n, n, n, 1.0, R2, n, R1, n, 0.0, P, n, kUp, 1, nullptr, info, s));
+    CQR2_HIP(launch_finalize_r(P, n, R, ldr, n, info, d_info, s));
+    th.end(5, s);
+    return hipSuccess;
+  }
+  // shifted CholeskyQR3: a third pass on Q, then R = R3 (R2 R1)
+  CQR2_HIP(launch_gemm(0, 0, n, n, n, 1.0, R2, n, R1, n, 0.0, P, n, kUp, 1, nullptr, info, s));
+  th.begin(0, s);
+  if (wide)
+    CQR2_HIP(launch_gram_wide(wp, 0, Q, m, (int)n, ldq, (double*)scratch, W, n, info, s));
+  else
+    CQR2_HIP(launch_gemm(1, 0, n, n, m, 1.0, Q, ldq, Q, ldq, 0.0, W, n, GEMM_C_LOWER, p.gram_splits,
+                         (double*)scratch, info, s));
+  th.end(0, s);
+  th.begin(2, s);
+  CQR2_HIP(cholinv_recursive(W, n, n, R1, n, Ri1, n, scratch, info, 2 * (int)n, s));  // R3, R3^-1
+  th.end(2, s);
+  th.begin(4, s);
+  if (wide) {  // in place: each workgroup reads only the rows it writes
+    CQR2_HIP(launch_upper_image(Ri1, n, (int)n, Uimg, s));
+    CQR2_HIP(launch_tall_gemm(0, Q, m, (int)n, ldq, Uimg, Q, ldq, info, s));
+  } else {     // the tiled GEMM reads A across output tiles: multiply into Q1, copy back
+    CQR2_HIP(launch_gemm(0, 0, m, n, n, 1.0, Q, ldq, Ri1, n, 0.0, (double*)Q1, m, GEMM_B_UPPER, 1, nullptr, info,
+                         s));
+    CQR2_HIP(hipMemcpy2DAsync(Q, ldq * sizeof(double), Q1, m * sizeof(double), m * sizeof(double), n,
+                              hipMemcpyDeviceToDevice, s));
+  }
+  th.end(4, s);
   th.begin(5, s);
-  CQR2_HIP(launch_gemm(0, 0, n, n, n, 1.0, R2, n, R1, n, 0.0, P, n, GEMM_A_UPPER | GEMM_B_UPPER | GEMM_C_UPPER, 1,
-                       nullptr, info, s));
-  CQR2_HIP(launch_finalize_r(P, n, R, ldr, n, info, d_info, s));
+  CQR2_HIP(launch_gemm(0, 0, n, n, n, 1.0, R1, n, P, n, 0.0, W, n, kUp, 1, nullptr, info, s));
+  CQR2_HIP(launch_finalize_r(W, n, R, ldr, n, info, d_info, s));
   th.end(5, s);
   return hipSuccess;
 }

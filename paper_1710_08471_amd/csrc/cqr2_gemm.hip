@@ -60,6 +60,14 @@ __device__ __forceinline__ double load_opB(const GemmArgs& g, int64_t k, int64_t
   return (double)(g.transB ? B[j + k * g.ldb] : B[k + j * g.ldb]);
 }
 
+// Entries outside a declared triangle are never read (they may hold anything).
+__device__ __forceinline__ bool a_in_triangle(const GemmArgs& g, int64_t i, int64_t k) {
+  return !((g.flags & GEMM_A_LOWER) && k > i) && !((g.flags & GEMM_A_UPPER) && k < i);
+}
+__device__ __forceinline__ bool b_in_triangle(const GemmArgs& g, int64_t k, int64_t j) {
+  return !((g.flags & GEMM_B_UPPER) && k > j) && !((g.flags & GEMM_B_LOWER) && k < j);
+}
+
 // Reduction range of output tile (i0, j0) for split `split` (triangular operands).
 __device__ __forceinline__ void gemm_krange(const GemmArgs& g, int64_t i0, int64_t j0, int split, int64_t& kb,
                                             int64_t& ke) {
@@ -101,11 +109,11 @@ __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
       int r, k;
       if (g.transA) { k = e & 15; r = e >> 4; } else { r = e & 63; k = e >> 6; }
       const int64_t gi = i0 + r, gk = k0 + k;
-      ra[t] = (gi < g.M && gk < ke) ? load_opA<TA>(g, gi, gk) : 0.0;
+      ra[t] = (gi < g.M && gk < ke && a_in_triangle(g, gi, gk)) ? load_opA<TA>(g, gi, gk) : 0.0;
       int kk, c;
       if (g.transB) { c = e & 63; kk = e >> 6; } else { kk = e & 15; c = e >> 4; }
       const int64_t bk = k0 + kk, gj = j0 + c;
-      rb[t] = (gj < g.N && bk < ke) ? load_opB<TB>(g, bk, gj) : 0.0;
+      rb[t] = (gj < g.N && bk < ke && b_in_triangle(g, bk, gj)) ? load_opB<TB>(g, bk, gj) : 0.0;
     }
   };
   auto sstore = [&](int buf) {
@@ -211,11 +219,11 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f32(GemmArgs g) {
       int r, k;
       if (g.transA) { k = e & 15; r = e >> 4; } else { r = e & 63; k = e >> 6; }
       const int64_t gi = i0 + r, gk = k0 + k;
-      ra[t] = (gi < g.M && gk < ke) ? (float)load_opA<double>(g, gi, gk) : 0.0f;
+      ra[t] = (gi < g.M && gk < ke && a_in_triangle(g, gi, gk)) ? (float)load_opA<double>(g, gi, gk) : 0.0f;
       int kk, c;
       if (g.transB) { c = e & 63; kk = e >> 6; } else { kk = e & 15; c = e >> 4; }
       const int64_t bk = k0 + kk, gj = j0 + c;
-      rb[t] = (gj < g.N && bk < ke) ? (float)load_opB<double>(g, bk, gj) : 0.0f;
+      rb[t] = (gj < g.N && bk < ke && b_in_triangle(g, bk, gj)) ? (float)load_opB<double>(g, bk, gj) : 0.0f;
     }
   };
   auto sstore = [&](int buf) {

@@ -61,6 +61,8 @@ hipError_t launch_apply_rinv(const double* A, int64_t m, int n, int64_t lda, con
                              int64_t ucs, double* Q, int64_t ldq, const int32_t* info, int num_cus, hipStream_t s);
 
 // ---- general FP64 GEMM: C = alpha op(A) op(B) + beta C ----------------------
+// Triangle flags are semantic: entries outside a declared triangle of A or B
+// are treated as zero and never read.
 enum GemmFlags {
   GEMM_A_LOWER = 1,  // op(A)(i, k) == 0 for k > i
   GEMM_A_UPPER = 2,  // op(A)(i, k) == 0 for k < i
@@ -134,7 +136,9 @@ struct GeneralPlan {
 GeneralPlan plan_general(int64_t m, int64_t n, bool mixed);
 hipError_t factor_general(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, int64_t ldq, double* R,
                           int64_t ldr, char* ws, const GeneralPlan& p, bool mixed, int32_t* d_info, hipStream_t s,
-                          const TimerHook& th);
+                          const TimerHook& th, bool shifted = false);
+// Adds s = 11 (m n + n (n + 1)) 2^-53 trace(W) to the diagonal of W (shifted CholeskyQR).
+hipError_t launch_shift_diag(double* W, int64_t ldw, int64_t n, int64_t m, const int32_t* info, hipStream_t s);
 
 // ---- multi-problem step (batched and serving paths, n <= 128) -------------
 // One launch advances every listed problem by one phase of CholeskyQR2:

@@ -79,7 +79,7 @@ def test_factor_ex_argument_errors():
     assert call(ldq=99) == -6
     assert call(ldr=9) == -8
     assert call(flags=7) == -12
-    assert call(flags=2) == -12
+    assert call(flags=3) == -12
     assert call(wb=lib.cqr2_workspace_size(100, 10, 1) - 1, flags=1) == -10
     assert call(work=NULL) == -9
     assert call(work=ctypes.c_void_p(0x40000008)) == -9           # not 256-byte aligned
@@ -97,6 +97,7 @@ def test_workspace_size_contract():
     assert lib.cqr2_workspace_size(1000, 200, 0) > 0      # general (tiled) path
     assert lib.cqr2_workspace_size(1000, 20, 1) > 0       # mixed precision (tiled path at any n)
     assert lib.cqr2_workspace_size(1000, 20, 3) == 0      # unknown flag bits
+    assert lib.cqr2_workspace_size(1000, 20, 2) == lib.cqr2_workspace_size(1000, 20, 0)   # shifted CQR3
     small = lib.cqr2_workspace_size(4096, 64, 0)
     big = lib.cqr2_workspace_size(1 << 20, 128, 0)
     assert 0 < small < big
