@@ -12,6 +12,7 @@ from .cqr2_ref import (  # noqa: F401
     cqr2_mixed,
     cholesky_shift,
     scqr3,
+    lstsq,
     syrk,
     upper_product,
 )

@@ -208,3 +208,21 @@ def scqr3(a: np.ndarray, return_intermediates: bool = False):
     if not return_intermediates:
         return q, r
     return q, r, {"shift": s, "R1": r1, "Q1": q1, "R2": r2, "R3": r3}
+
+
+def lstsq(a: np.ndarray, b: np.ndarray):
+    """Least-squares solution x = argmin ||A x - b|| from CholeskyQR2.
+
+    One of the uses the paper's Introduction names for the QR factorization
+    (least-squares problems): with
+    A = Q R, x = R^{-1} (Qᵀ b).  R^{-1} is applied as the method forms it,
+    through the explicit triangular inverses of the two passes,
+    R^{-1} = (R2 R1)^{-1} = R1^{-1} R2^{-1}.  b: m x k.
+    Returns (x, Q, R).
+    """
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    q, r, it = cqr2(a, return_intermediates=True)
+    c = q.T @ b
+    x = it["R1inv"] @ (it["R2inv"] @ c)
+    return x, q, r

@@ -359,3 +359,28 @@ def test_scqr3_pins_catch_a_missing_shift(monkeypatch):
     a = gdv_matrix(3000, 40, 1e12, 301)
     with pytest.raises(oracle.NotSPD):
         cqr2_ref.scqr3(a)
+
+
+# ---- least squares on top of the factorization (x = R^-1 Qᵀ b) ----
+
+@pytest.mark.parametrize("m,n,k,kappa,seed", [(500, 7, 1, 1e2, 501), (3000, 40, 3, 1e4, 502), (2000, 64, 2, 1e6, 503)])
+def test_lstsq_matches_lapack_and_is_optimal(m, n, k, kappa, seed):
+    a = gdv_matrix(m, n, kappa, seed)
+    rng = np.random.default_rng(seed)
+    b = a @ rng.standard_normal((n, k)) + 1e-3 * rng.standard_normal((m, k))   # inconsistent system
+    x, q, r = oracle.lstsq(a, b)
+    x_ref = np.linalg.lstsq(a, b, rcond=None)[0]
+    assert np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref) <= 50 * kappa * 2.0 ** -52 * 100
+    # optimality: the residual is orthogonal to range(A)
+    res = b - a @ x
+    assert np.linalg.norm(a.T @ res) <= 1e3 * 2.0 ** -52 * np.linalg.norm(a) * (
+        np.linalg.norm(a) * np.linalg.norm(x) + np.linalg.norm(b))
+
+
+def test_lstsq_exact_consistent_system():
+    """b = A x with A of orthogonal, power-of-two-norm columns: every step is
+    exact, so x comes back bit for bit."""
+    h = scipy.linalg.hadamard(64)[:, :8] * np.array([1.0, 2.0, 4.0, 0.5, 8.0, 1.0, 2.0, 0.25])
+    xt = np.arange(1.0, 9.0)[:, None]
+    x, q, r = oracle.lstsq(h, h @ xt)
+    assert np.array_equal(x, xt)
