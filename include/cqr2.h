@@ -101,6 +101,23 @@ int cqr2_factor_ex(const double* A, int64_t m, int64_t n, int64_t lda,
                    void* work, size_t work_bytes, int32_t* d_info,
                    uint32_t flags, void* stream);
 
+/* ---- least squares on top of the factorization -----------------------------
+ * cqr2_lstsq — X = argmin ||A X - B|| (the least-squares use of QR the
+ * paper's Introduction names), FP64: A = QR by CholeskyQR2 (written to Q, R
+ * as cqr2_factor_ex does), then X = R^{-1} (Qᵀ B) applied through the explicit
+ * triangular inverses of the two passes, R^{-1} = R1^{-1} R2^{-1}.
+ *   B: m x nrhs (ldb >= m), read only; X: n x nrhs (ldx >= n).
+ *   work: >= cqr2_lstsq_workspace_size(m, n, nrhs) bytes, 256-byte aligned.
+ *   d_info: as cqr2_factor_ex; on breakdown X and R are NaN.
+ * Argument indices for errors: A=1, m=2, n=3, lda=4, B=5, ldb=6, nrhs=7, X=8,
+ * ldx=9, Q=10, ldq=11, R=12, ldr=13, work=14, work_bytes=15, d_info=16.
+ */
+size_t cqr2_lstsq_workspace_size(int64_t m, int64_t n, int64_t nrhs);
+int cqr2_lstsq(const double* A, int64_t m, int64_t n, int64_t lda,
+               const double* B, int64_t ldb, int64_t nrhs, double* X, int64_t ldx,
+               double* Q, int64_t ldq, double* R, int64_t ldr,
+               void* work, size_t work_bytes, int32_t* d_info, void* stream);
+
 /* ---- the steps of one CholeskyQR pass, exposed individually --------------
  * These are the kernels cqr2_factor chains, with their own argument checks.
  */

@@ -42,6 +42,9 @@ SIGNATURES = {
     "cqr2_timing_reset": (_i32, []),
     "cqr2_timing_read": (_i32, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), _i32]),
     "cqr2_problem_check": (_i32, [_vp]),
+    "cqr2_lstsq_workspace_size": (_sz, [_i64, _i64, _i64]),
+    "cqr2_lstsq": (_i32, [_vp, _i64, _i64, _i64, _vp, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _sz, _vp,
+                          _vp]),
     "cqr2_batched_workspace_size": (_sz, [_vp, _i32, _u32]),
     "cqr2_factor_batched": (_i32, [_vp, _i32, _vp, _sz, _u32, _vp]),
     "cqr2_server_create": (_i32, [_sz, _sz, _i32, _vp, ctypes.POINTER(_vp)]),
@@ -248,6 +251,27 @@ def timing_read():
 
 def version() -> str:
     return load().cqr2_version().decode()
+
+
+def lstsq(A, B, info=None):
+    """(X, Q, R): least-squares solution of A X ~= B and the factorization (cqr2_lstsq)."""
+    import torch
+    lib = load()
+    _require_cuda_f64(A, "A")
+    _require_cuda_f64(B, "B")
+    m, n = A.shape
+    if B.dim() == 1:
+        B = B[:, None]
+    B = B if B.stride(0) == 1 else colmajor(B)
+    nrhs = B.shape[1]
+    X = empty_colmajor(n, nrhs, device=A.device)
+    Q = empty_colmajor(m, n, device=A.device)
+    R = empty_colmajor(n, n, device=A.device)
+    wb = lib.cqr2_lstsq_workspace_size(m, n, max(nrhs, 1))
+    work = torch.empty(max(int(wb), 256), dtype=torch.uint8, device=A.device)
+    _check(lib.cqr2_lstsq(_ptr(A), m, n, _ld(A), _ptr(B), m if nrhs == 0 else _ld(B), nrhs, _ptr(X), _ld(X), _ptr(Q),
+                          _ld(Q), _ptr(R), _ld(R), _ptr(work), work.numel(), _ptr(info), _stream()), "cqr2_lstsq")
+    return X, Q, R
 
 
 def problem(A, Q, R, info=None) -> Problem:

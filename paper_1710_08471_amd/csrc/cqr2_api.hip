@@ -231,6 +231,33 @@ int run_factor(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, in
 
 }  // namespace
 
+// ---- least squares ------------------------------------------------------------
+namespace {
+struct LstsqLayout {
+  size_t off_c = 0, off_t = 0, off_part = 0, total = 0;
+  int splits = 1;
+};
+
+LstsqLayout lstsq_layout(int64_t m, int64_t n, int64_t nrhs) {
+  LstsqLayout L;
+  size_t off = align_up(factor_workspace(m, n, CQR2_FP64));
+  const size_t cb = align_up((size_t)n * nrhs * sizeof(double));
+  L.off_c = off; off += cb;
+  L.off_t = off; off += cb;
+  L.splits = cqr2::gemm_pick_splits(n, nrhs, m, cqr2::kPlanCUs);
+  L.off_part = off; off += align_up(cqr2::gemm_workspace_bytes(n, nrhs, L.splits));
+  L.total = off;
+  return L;
+}
+
+// X = NaN after a breakdown (the solve's products skip their work then).
+__global__ void k_nan_if_info(double* X, int64_t ldx, int64_t rows, int64_t cols, const int32_t* info) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * cols || *info == 0) return;
+  X[(e % rows) + (e / rows) * ldx] = __builtin_nan("");
+}
+}  // namespace
+
 extern "C" {
 
 const char* cqr2_version(void) { return "cqr2-mi355x 0.2 (gfx950)"; }
@@ -317,6 +344,76 @@ int cqr2_factor(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, d
   void* ws = cached_workspace(factor_workspace(m, n, CQR2_FP64), &err);
   if (err) return err;
   return run_factor(A, m, n, lda, Q, lda, R, n, (char*)ws, nullptr, CQR2_FP64, (hipStream_t)stream);
+}
+
+size_t cqr2_lstsq_workspace_size(int64_t m, int64_t n, int64_t nrhs) {
+  if (m < n || n < 1 || nrhs < 1 || n > CQR2_MAX_N) return 0;
+  return lstsq_layout(m, n, nrhs).total;
+}
+
+int cqr2_lstsq(const double* A, int64_t m, int64_t n, int64_t lda, const double* B, int64_t ldb, int64_t nrhs,
+               double* X, int64_t ldx, double* Q, int64_t ldq, double* R, int64_t ldr, void* work, size_t work_bytes,
+               int32_t* d_info, void* stream) {
+  if (n < 0) return -3;
+  if (m < n) return -2;
+  if (lda < (m > 1 ? m : 1)) return -4;
+  if (ldb < (m > 1 ? m : 1)) return -6;
+  if (nrhs < 0) return -7;
+  if (ldx < (n > 1 ? n : 1)) return -9;
+  if (ldq < (m > 1 ? m : 1)) return -11;
+  if (ldr < (n > 1 ? n : 1)) return -13;
+  if (n == 0) return 0;
+  if (A == nullptr || !aligned8(A)) return -1;
+  if (nrhs > 0 && (B == nullptr || !aligned8(B))) return -5;
+  if (nrhs > 0 && (X == nullptr || !aligned8(X))) return -8;
+  if (Q == nullptr || !aligned8(Q)) return -10;
+  if (R == nullptr || !aligned8(R)) return -12;
+  if (d_info != nullptr && ((uintptr_t)d_info & 3u) != 0) return -16;
+  if (n > CQR2_MAX_N) return CQR2_ERR_UNSUPPORTED;
+  const size_t ab = matrix_bytes(m, n, lda), bb = matrix_bytes(m, nrhs, ldb), xb = matrix_bytes(n, nrhs, ldx);
+  const size_t qb = matrix_bytes(m, n, ldq), rb = matrix_bytes(n, n, ldr);
+  if (overlaps(X, xb, A, ab) || overlaps(X, xb, B, bb)) return -8;
+  if (overlaps(Q, qb, A, ab) || overlaps(Q, qb, B, bb) || overlaps(Q, qb, X, xb)) return -10;
+  if (overlaps(R, rb, A, ab) || overlaps(R, rb, B, bb) || overlaps(R, rb, X, xb) || overlaps(R, rb, Q, qb))
+    return -12;
+  const LstsqLayout L = lstsq_layout(m, n, nrhs > 0 ? nrhs : 1);
+  if (work == nullptr || ((uintptr_t)work % kAlign) != 0) return -14;
+  if (work_bytes < L.total) return -15;
+  if (overlaps(work, work_bytes, A, ab) || overlaps(work, work_bytes, B, bb) || overlaps(work, work_bytes, X, xb) ||
+      overlaps(work, work_bytes, Q, qb) || overlaps(work, work_bytes, R, rb))
+    return -14;
+  hipStream_t s = (hipStream_t)stream;
+  char* ws = (char*)work;
+  const int rc = run_factor(A, m, n, lda, Q, ldq, R, ldr, ws, d_info, CQR2_FP64, s);
+  if (rc != 0 || nrhs == 0) return rc;
+  const int32_t* info = (const int32_t*)ws;  // both layouts keep the info word first
+  double* C = (double*)(ws + L.off_c);
+  double* T = (double*)(ws + L.off_t);
+  // C = Qᵀ B
+  CQR2_TRY(cqr2::launch_gemm(1, 0, n, nrhs, m, 1.0, Q, ldq, B, ldb, 0.0, C, n, 0, L.splits,
+                             (double*)(ws + L.off_part), info, s));
+  // T = R2^{-1} C, X = R1^{-1} T
+  if (use_small(n, CQR2_FP64)) {
+    // row-major U images: U[i np + k] = R^{-1}(i, k), i.e. op(A) = Aᵀ of a column-major np x np view
+    const SmallLayout SL = make_small_layout(m, n);
+    const double* U1 = (const double*)(ws + SL.off_u1);
+    const double* U2 = (const double*)(ws + SL.off_u2);
+    CQR2_TRY(cqr2::launch_gemm(1, 0, n, nrhs, n, 1.0, U2, SL.np, C, n, 0.0, T, n, cqr2::GEMM_A_UPPER, 1, nullptr,
+                               info, s));
+    CQR2_TRY(cqr2::launch_gemm(1, 0, n, nrhs, n, 1.0, U1, SL.np, T, n, 0.0, X, ldx, cqr2::GEMM_A_UPPER, 1, nullptr,
+                               info, s));
+  } else {
+    const cqr2::GeneralPlan p = cqr2::plan_general(m, n, false);
+    const double* Ri1 = (const double*)(ws + p.off_ri1);
+    const double* Ri2 = (const double*)(ws + p.off_ri2);
+    CQR2_TRY(cqr2::launch_gemm(0, 0, n, nrhs, n, 1.0, Ri2, n, C, n, 0.0, T, n, cqr2::GEMM_A_UPPER, 1, nullptr, info,
+                               s));
+    CQR2_TRY(cqr2::launch_gemm(0, 0, n, nrhs, n, 1.0, Ri1, n, T, n, 0.0, X, ldx, cqr2::GEMM_A_UPPER, 1, nullptr,
+                               info, s));
+  }
+  const int64_t total = n * nrhs;
+  hipLaunchKernelGGL(k_nan_if_info, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, X, ldx, n, nrhs, info);
+  return check_hip(hipGetLastError());
 }
 
 size_t cqr2_gram_workspace_size(int64_t m, int64_t n) {

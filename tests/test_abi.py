@@ -190,3 +190,34 @@ def test_server_argument_errors():
     assert lib.cqr2_server_step(NULL, None, None) == -1
     assert lib.cqr2_server_clock(NULL) == -1
     assert lib.cqr2_server_destroy(NULL) == -1
+
+
+def test_lstsq_argument_errors():
+    lib = cq.load()
+    f = lib.cqr2_lstsq
+    A, B, X = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x1000000), ctypes.c_void_p(0x2000000)
+    Q, R, W = ctypes.c_void_p(0x3000000), ctypes.c_void_p(0x4000000), ctypes.c_void_p(0x5000000)
+    ws = lib.cqr2_lstsq_workspace_size(100, 10, 2)
+    assert ws > lib.cqr2_workspace_size(100, 10, 0) and ws % 256 == 0
+    assert lib.cqr2_lstsq_workspace_size(10, 20, 1) == 0
+    ok = dict(A=A, m=100, n=10, lda=100, B=B, ldb=100, k=2, X=X, ldx=10, Q=Q, ldq=100, R=R, ldr=10, W=W, wb=ws,
+              info=NULL)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return f(a["A"], a["m"], a["n"], a["lda"], a["B"], a["ldb"], a["k"], a["X"], a["ldx"], a["Q"], a["ldq"],
+                 a["R"], a["ldr"], a["W"], a["wb"], a["info"], NULL)
+
+    assert call(n=-1) == -3
+    assert call(m=5) == -2
+    assert call(ldb=99) == -6
+    assert call(k=-1) == -7
+    assert call(ldx=9) == -9
+    assert call(ldq=99) == -11
+    assert call(ldr=9) == -13
+    assert call(B=NULL) == -5
+    assert call(X=ctypes.c_void_p(0x10000 + 8)) == -8          # X overlaps A
+    assert call(R=ctypes.c_void_p(0x3000000 + 8)) == -12       # R overlaps Q
+    assert call(W=ctypes.c_void_p(0x5000008)) == -14
+    assert call(wb=ws - 1) == -15
+    assert call(info=ctypes.c_void_p(0x6000002)) == -16
