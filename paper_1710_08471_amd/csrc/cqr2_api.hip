@@ -420,8 +420,7 @@ size_t cqr2_gram_workspace_size(int64_t m, int64_t n) {
   if (m < 0 || n < 1 || n > CQR2_MAX_N) return 0;
   if (n <= kSmallN) return align_up(cqr2::plan_gram(m, n).partial_bytes);
   if (n <= cqr2::kWideMaxN) return align_up(cqr2::plan_gram_wide(m).partial_bytes);
-  const int splits = cqr2::gemm_pick_splits(n, n, m, cqr2::kPlanCUs);
-  return align_up(cqr2::gemm_workspace_bytes(n, n, splits) + 8);
+  return align_up(cqr2::plan_syrk(m, n).partial_bytes);
 }
 
 int cqr2_gram(const double* A, int64_t m, int64_t n, int64_t lda, double* W, int64_t ldw, void* work,
@@ -454,10 +453,8 @@ int cqr2_gram(const double* A, int64_t m, int64_t n, int64_t lda, double* W, int
     CQR2_TRY(cqr2::launch_mirror_lower(W, ldw, n, s));
     return 0;
   }
-  // n > 256: lower triangle by the GEMM, then mirrored.
-  const int splits = cqr2::gemm_pick_splits(n, n, m, cqr2::kPlanCUs);
-  CQR2_TRY(cqr2::launch_gemm(1, 0, n, n, m, 1.0, A, lda, A, lda, 0.0, W, ldw, cqr2::GEMM_C_LOWER, splits,
-                             (double*)work, nullptr, s));
+  // n > 256: lower triangle by 128 x 128 tiles, then mirrored.
+  CQR2_TRY(cqr2::launch_syrk(cqr2::plan_syrk(m, n), A, m, (int)n, lda, (double*)work, W, ldw, nullptr, s));
   CQR2_TRY(cqr2::launch_mirror_lower(W, ldw, n, s));
   return 0;
 }
@@ -519,27 +516,26 @@ int cqr2_apply_rinv(const double* A, int64_t m, int64_t n, int64_t lda, const do
     CQR2_TRY(cqr2::launch_apply_rinv(A, m, (int)n, lda, U, 1, ldu, Q, ldq, nullptr, device_cus(), s));
     return 0;
   }
-  if (n <= cqr2::kWideMaxN) {  // each workgroup reads only the rows it writes: in place is safe
-    int err = 0;
-    double* ut = (double*)cached_workspace(cqr2::kUpperImageBytes, &err);
-    if (err) return err;
-    CQR2_TRY(cqr2::launch_upper_image(U, ldu, (int)n, ut, s));  // row-major image of U
-    CQR2_TRY(cqr2::launch_tall_gemm(0, A, m, (int)n, lda, ut, Q, ldq, nullptr, s));
-    return 0;
-  }
+  // the tall kernel reads U as its zero-padded row-major image; with several
+  // 256-column tiles (n > 256) a row block is read across tiles, so an
+  // in-place product multiplies from a copy of A
+  const bool copy_a = in_place && n > cqr2::kWideMaxN;
+  const size_t img = align_up(cqr2::upper_image_bytes(n));
+  int err = 0;
+  char* ws = (char*)cached_workspace(img + (copy_a ? (size_t)m * n * sizeof(double) : 0), &err);
+  if (err) return err;
+  double* ut = (double*)ws;
+  CQR2_TRY(cqr2::launch_upper_image(U, ldu, (int)n, ut, s));
   const double* src = A;
   int64_t lds = lda;
-  if (in_place) {  // the tiled GEMM reads A across output tiles: multiply from a copy
-    int err = 0;
-    double* tmp = (double*)cached_workspace((size_t)m * n * sizeof(double), &err);
-    if (err) return err;
+  if (copy_a) {
+    double* tmp = (double*)(ws + img);
     CQR2_TRY(hipMemcpy2DAsync(tmp, m * sizeof(double), A, lda * sizeof(double), m * sizeof(double), n,
                               hipMemcpyDeviceToDevice, s));
     src = tmp;
     lds = m;
   }
-  CQR2_TRY(cqr2::launch_gemm(0, 0, m, n, n, 1.0, src, lds, U, ldu, 0.0, Q, ldq, cqr2::GEMM_B_UPPER, 1, nullptr,
-                             nullptr, s));
+  CQR2_TRY(cqr2::launch_tall_gemm(0, src, m, (int)n, lds, ut, Q, ldq, nullptr, s));
   return 0;
 }
 

@@ -183,9 +183,10 @@ GeneralPlan plan_general(int64_t m, int64_t n, bool mixed) {
   p.off_r2 = take(nn);
   p.off_ri2 = take(nn);
   p.off_p = take(nn);
-  p.off_uimg = n <= kWideMaxN ? take(kUpperImageBytes) : 0;
+  p.off_uimg = take(upper_image_bytes(n));
   size_t gws = gemm_workspace_bytes(n, n, p.gram_splits);
   if (n <= kWideMaxN) gws = plan_gram_wide(m).partial_bytes;
+  else if (plan_syrk(m, n).partial_bytes > gws) gws = plan_syrk(m, n).partial_bytes;
   const size_t rws = cholinv_rec_workspace(n);
   p.off_scratch = take(gws > rws ? gws : rws);
   p.off_q1 = take((size_t)m * n * (mixed ? sizeof(float) : sizeof(double)));
@@ -210,35 +211,33 @@ hipError_t factor_general(const double* A, int64_t m, int64_t n, int64_t lda, do
   // n <= 256: tall-skinny kernels (A read once per step); above: tiled GEMMs
   const bool wide = n <= kWideMaxN;
   const WideGramPlan wp = plan_gram_wide(m);
+  const SyrkPlan sp = wide ? SyrkPlan{} : plan_syrk(m, n);
   CQR2_HIP(launch_set_info(info, 0, s));
   // pass 1: CQR(A) -> Q1 (workspace), R1
   th.begin(0, s);
   if (wide)
     CQR2_HIP(launch_gram_wide(wp, 0, A, m, (int)n, lda, (double*)scratch, W, n, info, s));
   else
-    CQR2_HIP(launch_gemm(1, 0, n, n, m, 1.0, A, lda, A, lda, 0.0, W, n, GEMM_C_LOWER, p.gram_splits,
-                         (double*)scratch, info, s));
+    CQR2_HIP(launch_syrk(sp, A, m, (int)n, lda, (double*)scratch, W, n, info, s));
   th.end(0, s);
   if (shifted) CQR2_HIP(launch_shift_diag(W, n, n, m, info, s));
   th.begin(2, s);
   CQR2_HIP(cholinv_recursive(W, n, n, R1, n, Ri1, n, scratch, info, 0, s));
   th.end(2, s);
   th.begin(3, s);
-  // the tall kernels read R^{-1} as its zero-padded row-major image
-  if (wide) CQR2_HIP(launch_upper_image(Ri1, n, (int)n, Uimg, s));
-  if (mixed && wide)
+  // the tall kernel reads R^{-1} as its zero-padded row-major image
+  CQR2_HIP(launch_upper_image(Ri1, n, (int)n, Uimg, s));
+  if (mixed)
     CQR2_HIP(launch_tall_gemm_f32(A, m, (int)n, lda, Uimg, (float*)Q1, m, info, s));
-  else if (mixed)
-    CQR2_HIP(launch_gemm_f32(0, 0, m, n, n, A, lda, Ri1, n, (float*)Q1, m, GEMM_B_UPPER, info, s));
-  else if (wide)
-    CQR2_HIP(launch_tall_gemm(0, A, m, (int)n, lda, Uimg, (double*)Q1, m, info, s));
   else
-    CQR2_HIP(launch_gemm(0, 0, m, n, n, 1.0, A, lda, Ri1, n, 0.0, (double*)Q1, m, GEMM_B_UPPER, 1, nullptr, info, s));
+    CQR2_HIP(launch_tall_gemm(0, A, m, (int)n, lda, Uimg, (double*)Q1, m, info, s));
   th.end(3, s);
   // pass 2: CQR(Q1) -> Q, R2, on the stored Q1 values (FP32 ones widen exactly)
   th.begin(0, s);
   if (wide)
     CQR2_HIP(launch_gram_wide(wp, q1f, Q1, m, (int)n, m, (double*)scratch, W, n, info, s));
+  else if (!mixed)
+    CQR2_HIP(launch_syrk(sp, (const double*)Q1, m, (int)n, m, (double*)scratch, W, n, info, s));
   else
     CQR2_HIP(launch_gemm_in32(q1f, q1f, 1, 0, n, n, m, 1.0, Q1, m, Q1, m, 0.0, W, n, GEMM_C_LOWER, p.gram_splits,
                               (double*)scratch, info, s));
@@ -247,13 +246,8 @@ hipError_t factor_general(const double* A, int64_t m, int64_t n, int64_t lda, do
   CQR2_HIP(cholinv_recursive(W, n, n, R2, n, Ri2, n, scratch, info, (int)n, s));
   th.end(2, s);
   th.begin(4, s);
-  if (wide) {
-    CQR2_HIP(launch_upper_image(Ri2, n, (int)n, Uimg, s));
-    CQR2_HIP(launch_tall_gemm(q1f, Q1, m, (int)n, m, Uimg, Q, ldq, info, s));
-  }
-  else
-    CQR2_HIP(launch_gemm_in32(q1f, 0, 0, 0, m, n, n, 1.0, Q1, m, Ri2, n, 0.0, Q, ldq, GEMM_B_UPPER, 1, nullptr,
-                              info, s));
+  CQR2_HIP(launch_upper_image(Ri2, n, (int)n, Uimg, s));
+  CQR2_HIP(launch_tall_gemm(q1f, Q1, m, (int)n, m, Uimg, Q, ldq, info, s));
   th.end(4, s);
   constexpr int kUp = GEMM_A_UPPER | GEMM_B_UPPER | GEMM_C_UPPER;
   if (!shifted) {
@@ -270,19 +264,17 @@ hipError_t factor_general(const double* A, int64_t m, int64_t n, int64_t lda, do
   if (wide)
     CQR2_HIP(launch_gram_wide(wp, 0, Q, m, (int)n, ldq, (double*)scratch, W, n, info, s));
   else
-    CQR2_HIP(launch_gemm(1, 0, n, n, m, 1.0, Q, ldq, Q, ldq, 0.0, W, n, GEMM_C_LOWER, p.gram_splits,
-                         (double*)scratch, info, s));
+    CQR2_HIP(launch_syrk(sp, Q, m, (int)n, ldq, (double*)scratch, W, n, info, s));
   th.end(0, s);
   th.begin(2, s);
   CQR2_HIP(cholinv_recursive(W, n, n, R1, n, Ri1, n, scratch, info, 2 * (int)n, s));  // R3, R3^-1
   th.end(2, s);
   th.begin(4, s);
-  if (wide) {  // in place: each workgroup reads only the rows it writes
-    CQR2_HIP(launch_upper_image(Ri1, n, (int)n, Uimg, s));
+  CQR2_HIP(launch_upper_image(Ri1, n, (int)n, Uimg, s));
+  if (wide) {  // in place: with one column tile each workgroup reads only the rows it writes
     CQR2_HIP(launch_tall_gemm(0, Q, m, (int)n, ldq, Uimg, Q, ldq, info, s));
-  } else {     // the tiled GEMM reads A across output tiles: multiply into Q1, copy back
-    CQR2_HIP(launch_gemm(0, 0, m, n, n, 1.0, Q, ldq, Ri1, n, 0.0, (double*)Q1, m, GEMM_B_UPPER, 1, nullptr, info,
-                         s));
+  } else {     // several column tiles read a row block across tiles: multiply into Q1, copy back
+    CQR2_HIP(launch_tall_gemm(0, Q, m, (int)n, ldq, Uimg, (double*)Q1, m, info, s));
     CQR2_HIP(hipMemcpy2DAsync(Q, ldq * sizeof(double), Q1, m * sizeof(double), m * sizeof(double), n,
                               hipMemcpyDeviceToDevice, s));
   }

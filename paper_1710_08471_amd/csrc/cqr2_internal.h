@@ -100,17 +100,33 @@ WideGramPlan plan_gram_wide(int64_t m);
 // Lower triangle of W = AᵀA (n <= 256); A is FP64, or FP32 when a_f32.
 hipError_t launch_gram_wide(const WideGramPlan& p, int a_f32, const void* A, int64_t m, int n, int64_t lda,
                             double* partials, double* W, int64_t ldw, const int32_t* info, hipStream_t s);
-// Zero-padded 256 x 256 row-major image of the upper triangle of X (n x n,
-// column-major, ldx): the form of U the tall kernels read.
-constexpr int64_t kUpperImageBytes = 256 * 256 * sizeof(double);
+// Zero-padded row-major image of the upper triangle of X (n x n, column-major,
+// ldx): the form of U the tall kernels read; upper_image_ld(n) = n rounded up
+// to 256 is both its leading dimension and its row count.
+int64_t upper_image_ld(int64_t n);
+inline size_t upper_image_bytes(int64_t n) {
+  const size_t ld = (size_t)((n + 255) / 256 * 256);
+  return ld * ld * sizeof(double);
+}
 hipError_t launch_upper_image(const double* X, int64_t ldx, int n, double* T, hipStream_t s);
-// Q = A U (n <= 256, U given as its upper image); A FP64 or FP32 (a_f32), FP64
-// arithmetic.
+// Q = A U (U given as its upper image); A FP64 or FP32 (a_f32), FP64
+// arithmetic.  Reads rows of A across 256-column tiles: not in place for n > 256.
 hipError_t launch_tall_gemm(int a_f32, const void* A, int64_t m, int n, int64_t lda, const double* Uimg, double* Q,
                             int64_t ldq, const int32_t* info, hipStream_t s);
-// Q(float) = fl32(A) fl32(U) with FP32 products and sums (n <= 256).
+// Q(float) = fl32(A) fl32(U) with FP32 products and sums.
 hipError_t launch_tall_gemm_f32(const double* A, int64_t m, int n, int64_t lda, const double* Uimg, float* Q,
                                 int64_t ldq, const int32_t* info, hipStream_t s);
+
+// ---- Gram for n > 256 by 128 x 128 tiles --------------------------------------
+struct SyrkPlan {
+  int npairs = 0, splits = 0;             // lower tile pairs, row splits
+  int64_t stages = 0, stages_per_wg = 0;  // 32-row stages
+  size_t partial_bytes = 0;
+};
+SyrkPlan plan_syrk(int64_t m, int64_t n);
+// Lower triangle of W = AᵀA (FP64 A, any n).
+hipError_t launch_syrk(const SyrkPlan& p, const double* A, int64_t m, int n, int64_t lda, double* partials,
+                       double* W, int64_t ldw, const int32_t* info, hipStream_t s);
 
 // ---- recursive CholInv and the n > 128 driver --------------------------------
 int64_t cholinv_split(int64_t n);

@@ -231,12 +231,167 @@ hipError_t launch_gram_wide(const WideGramPlan& p, int a_f32, const void* A, int
 }
 
 // ============================================================================
-// Q = A U for upper-triangular U, n <= 256 (Algorithm 4 step 3).
+// Gram for n > 256, by 128 x 128 tiles of its lower triangle.
 //
-// U comes as a zero-padded 256 x 256 row-major image (U(k, j) at U[256 k + j],
-// zero outside the n x n upper triangle), so a chunk of 16 rows of U is
-// 32 KB of contiguous memory.  A workgroup owns 128 rows of A and all output
-// columns: 8 waves, wave w covers rows 64 (w / 4) .. +64 and a 64-column
+// Workgroup (tile pair (I, J), I >= J; row split s) streams the two column
+// panels A(:, 128 I ..) and A(:, 128 J ..) of its rows through LDS in 32-row
+// stages (direct 16-byte copies, the swizzle of the n <= 256 kernel, double
+// buffered: 2 x 2 x 32 KB; a diagonal pair loads one panel) and accumulates
+// W(128 I + .., 128 J + ..) with MFMA 16x16x4: wave w owns the 16 rows
+// 16 w .. of the tile and its eight 16 x 16 tiles (the lower ones only on a
+// diagonal pair).  Partial tiles are summed over the row splits in a fixed
+// order by k_syrk_reduce.
+// ============================================================================
+constexpr int kSyT = 128;                   // output tile (columns per panel)
+constexpr int kSyBuf = kSyT * kWideRows;    // doubles per panel stage
+constexpr int kSyTile = kSyT * kSyT;        // doubles per partial tile
+
+__device__ __forceinline__ void syrk_pair(int t, int& I, int& J) {
+  int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while (i * (i + 1) / 2 > t) --i;
+  while ((i + 1) * (i + 2) / 2 <= t) ++i;
+  I = i;
+  J = t - i * (i + 1) / 2;
+}
+
+__global__ __launch_bounds__(512, 1) void k_syrk_tile(const double* __restrict__ A, int64_t m, int n, int64_t lda,
+                                                      int64_t stages, int64_t spw, double* __restrict__ partials,
+                                                      int npairs, const int32_t* __restrict__ info) {
+  __shared__ __attribute__((aligned(16))) double lds[2 * 2 * kSyBuf];
+  if (info != nullptr && *info != 0) return;
+  int TI, TJ;
+  syrk_pair(blockIdx.x, TI, TJ);
+  const bool diag = TI == TJ;
+  const int64_t st0 = (int64_t)blockIdx.y * spw;
+  const int64_t st1 = st0 + spw < stages ? st0 + spw : stages;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int colI = kSyT * TI, colJ = kSyT * TJ;
+  const bool direct_ok = (((uintptr_t)A & 15u) == 0) && ((lda & 1) == 0);
+
+  // columns >= n are never loaded: zero them in every buffer once
+  for (int e = tid; e < 4 * kSyBuf; e += 512) {
+    const int panel = (e / kSyBuf) & 1;  // buffers: [stage 0: I, J][stage 1: I, J]
+    const int c = (e % kSyBuf) / kWideRows;
+    if ((panel == 0 ? colI : colJ) + c >= n) lds[e] = 0.0;
+  }
+  auto fill_panel = [&](int64_t st, int col0, double* buf) {
+    const int64_t row0 = st * kWideRows;
+    if (direct_ok && row0 + kWideRows <= m) {
+      const int sub = lane >> 4, lrow = 2 * (lane & 15);
+      for (int p = w; p < kSyT / 4; p += 8) {
+        const int c = 4 * p + sub;
+        if (col0 + c < n) {
+          const int grow = lrow ^ ((c & 15) << 1);
+          __builtin_amdgcn_global_load_lds((const void*)(A + row0 + grow + (int64_t)(col0 + c) * lda),
+                                           (__attribute__((address_space(3))) void*)(buf + 4 * p * kWideRows), 16, 0,
+                                           0);
+        }
+      }
+    } else {
+      for (int e = tid; e < kSyBuf; e += 512) {
+        const int c = e / kWideRows, r = e % kWideRows;
+        const int64_t row = row0 + r;
+        buf[wide_pos(c, r)] = (row < m && col0 + c < n) ? A[row + (int64_t)(col0 + c) * lda] : 0.0;
+      }
+    }
+  };
+  auto fill = [&](int64_t st, int b) {
+    fill_panel(st, colI, lds + (2 * b) * kSyBuf);
+    if (!diag) fill_panel(st, colJ, lds + (2 * b + 1) * kSyBuf);
+  };
+
+  wd4 acc[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) acc[c] = wd4{0.0, 0.0, 0.0, 0.0};
+  __syncthreads();
+  if (st0 < st1) fill(st0, 0);
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  const int fc = lane & 15, fk = lane >> 4;
+  const bool row_live = colI + 16 * w < n;
+  for (int64_t st = st0; st < st1; ++st) {
+    const int b = (int)((st - st0) & 1);
+    const double* bI = lds + (2 * b) * kSyBuf;
+    const double* bJ = diag ? bI : lds + (2 * b + 1) * kSyBuf;
+    if (st + 1 < st1) fill(st + 1, b ^ 1);
+    if (row_live) {
+#pragma unroll 1
+      for (int k0 = 0; k0 < kWideRows; k0 += 4) {
+        const double fi = bI[wide_pos(16 * w + fc, k0 + fk)];
+        double fj[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) fj[c] = bJ[wide_pos(16 * c + fc, k0 + fk)];
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+          if ((!diag || c <= w) && colJ + 16 * c < n)  // uniform
+            acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(fi, fj[c], acc[c], 0, 0, 0);
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+  }
+  double* out = partials + ((int64_t)blockIdx.y * npairs + blockIdx.x) * kSyTile;
+#pragma unroll
+  for (int c = 0; c < 8; ++c)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) out[((w * 8 + c) * 4 + r) * 64 + lane] = acc[c][r];
+}
+
+// W(lower) = sum over the splits, in split order, of the partial tiles.
+__global__ __launch_bounds__(256) void k_syrk_reduce(const double* __restrict__ part, int splits, int npairs, int n,
+                                                     double* __restrict__ W, int64_t ldw,
+                                                     const int32_t* __restrict__ info) {
+  if (info != nullptr && *info != 0) return;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)npairs * kSyTile) return;
+  const int pair = (int)(e / kSyTile), x = (int)(e % kSyTile);
+  int TI, TJ;
+  syrk_pair(pair, TI, TJ);
+  const int w = x >> 11, c = (x >> 8) & 7, r = (x >> 6) & 3, l = x & 63;
+  const int row = kSyT * TI + 16 * w + 4 * r + (l >> 4), col = kSyT * TJ + 16 * c + (l & 15);
+  if (row >= n || col > row) return;
+  double v = 0.0;
+  for (int s = 0; s < splits; ++s) v += part[(int64_t)s * npairs * kSyTile + e];
+  W[row + (int64_t)col * ldw] = v;
+}
+
+SyrkPlan plan_syrk(int64_t m, int64_t n) {
+  SyrkPlan p{};
+  const int t = (int)((n + kSyT - 1) / kSyT);
+  p.npairs = t * (t + 1) / 2;
+  p.stages = m > 0 ? (m + kWideRows - 1) / kWideRows : 1;
+  // at least four workgroups per CU of a 256-CU device, at least 64 stages (2048 rows) each
+  int64_t s = (4 * 256 + p.npairs - 1) / p.npairs;
+  const int64_t smax = p.stages / 64 > 0 ? p.stages / 64 : 1;
+  if (s > smax) s = smax;
+  if (s < 1) s = 1;
+  p.stages_per_wg = (p.stages + s - 1) / s;
+  p.splits = (int)((p.stages + p.stages_per_wg - 1) / p.stages_per_wg);
+  p.partial_bytes = (size_t)p.splits * p.npairs * kSyTile * sizeof(double);
+  return p;
+}
+
+hipError_t launch_syrk(const SyrkPlan& p, const double* A, int64_t m, int n, int64_t lda, double* partials,
+                       double* W, int64_t ldw, const int32_t* info, hipStream_t s) {
+  hipLaunchKernelGGL(k_syrk_tile, dim3(p.npairs, p.splits), dim3(512), 0, s, A, m, n, lda, p.stages, p.stages_per_wg,
+                     partials, p.npairs, info);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t total = (int64_t)p.npairs * kSyTile;
+  hipLaunchKernelGGL(k_syrk_reduce, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, partials, p.splits,
+                     p.npairs, n, W, ldw, info);
+  return hipGetLastError();
+}
+
+// ============================================================================
+// Q = A U for upper-triangular U (Algorithm 4 step 3).
+//
+// U comes as a zero-padded row-major image (U(k, j) at U[ld k + j], ld = n
+// rounded up to 256, zero outside the n x n upper triangle), so a chunk of 16
+// rows of U for 256 columns is 32 KB of contiguous memory.  A workgroup owns
+// 128 rows of A and 256 output columns (grid.y walks the column tiles; the
+// reduction stops at the tile's last column, U(k, j) = 0 for k > j): 8 waves, wave w covers rows 64 (w / 4) .. +64 and a 64-column
 // group; the two waves sharing a SIMD (w, w + 4) get the lightest and the
 // heaviest share of the triangle.  The reduction walks 16-column chunks of A
 // and 16-row chunks of U, both copied straight from global memory into a
@@ -263,8 +418,8 @@ __device__ __forceinline__ int tall_wave_col0(int w) {
 
 template <typename TA, bool F32MATH>
 __global__ __launch_bounds__(512, 1) void k_tall(const TA* __restrict__ A, int64_t m, int n, int64_t lda,
-                                                 const double* __restrict__ U, void* __restrict__ Qv, int64_t ldq,
-                                                 const int32_t* __restrict__ info) {
+                                                 const double* __restrict__ U, int64_t ldu, void* __restrict__ Qv,
+                                                 int64_t ldq, const int32_t* __restrict__ info) {
   constexpr int kABytes = kTallK * kTallRows * (int)sizeof(TA);
   constexpr int kUBytes = kTallK * kTallUld * 8;
   constexpr int kBufBytes = kABytes + kUBytes;
@@ -275,10 +430,12 @@ __global__ __launch_bounds__(512, 1) void k_tall(const TA* __restrict__ A, int64
   __shared__ __attribute__((aligned(16))) char smem[kTallBufs * kBufBytes];
   if (info != nullptr && *info != 0) return;
   const int64_t i0 = (int64_t)blockIdx.x * kTallRows;
+  const int j0 = (int)blockIdx.y * kTallUld;  // this workgroup's 256 output columns
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int wr = 64 * (wave >> 2), wc = tall_wave_col0(wave);
-  const int nchunks = (n + kTallK - 1) / kTallK;
+  const int wr = 64 * (wave >> 2), wc = j0 + tall_wave_col0(wave);  // wc: global column of the wave's group
+  const int kend = n < j0 + kTallUld ? n : j0 + kTallUld;           // U(k, j) = 0 for k > j
+  const int nchunks = (kend + kTallK - 1) / kTallK;
   const bool direct = (i0 + kTallRows <= m) && (((uintptr_t)A & 15u) == 0) &&
                       (((lda * (int64_t)sizeof(TA)) & 15) == 0);
 
@@ -321,7 +478,7 @@ __global__ __launch_bounds__(512, 1) void k_tall(const TA* __restrict__ A, int64
     for (int t = 0; t < kUInstr; ++t) {
       const int h = 4 * wave + t;  // half-row h/2 of the chunk, 128 doubles
       const int kr = h >> 1, c0 = 128 * (h & 1);
-      __builtin_amdgcn_global_load_lds((const void*)(U + (int64_t)(k0 + kr) * kTallUld + c0 + 2 * lane),
+      __builtin_amdgcn_global_load_lds((const void*)(U + (int64_t)(k0 + kr) * ldu + j0 + c0 + 2 * lane),
                                        (__attribute__((address_space(3))) void*)(Us + kr * kTallUld + c0), 16, 0, 0);
     }
   };
@@ -359,7 +516,7 @@ __global__ __launch_bounds__(512, 1) void k_tall(const TA* __restrict__ A, int64
             if (wc + 16 * q + 15 >= k0 + ks) {
               double b[4];
 #pragma unroll
-              for (int c = 0; c < 4; ++c) b[c] = Us[kk * kTallUld + wc + 16 * q + 4 * c + bc];
+              for (int c = 0; c < 4; ++c) b[c] = Us[kk * kTallUld + (wc - j0) + 16 * q + 4 * c + bc];
 #pragma unroll
               for (int c = 0; c < 4; ++c)
 #pragma unroll
@@ -408,7 +565,7 @@ __global__ __launch_bounds__(512, 1) void k_tall(const TA* __restrict__ A, int64
 #pragma unroll
           for (int rt = 0; rt < 4; ++rt) a[rt] = (float)As[kk * kTallRows + wr + 16 * rt + l16];
 #pragma unroll
-          for (int ct = 0; ct < 4; ++ct) u[ct] = (float)Us[kk * kTallUld + wc + 16 * ct + l16];
+          for (int ct = 0; ct < 4; ++ct) u[ct] = (float)Us[kk * kTallUld + (wc - j0) + 16 * ct + l16];
 #pragma unroll
           for (int ct = 0; ct < 4; ++ct) {
             if (wc + 16 * ct + 15 >= k0 + ks) {
@@ -436,10 +593,11 @@ __global__ __launch_bounds__(512, 1) void k_tall(const TA* __restrict__ A, int64
   }
 }
 
-// Row-major, zero-padded 256 x 256 image of the upper triangle of an n x n
-// column-major X (ldx): T[256 k + j] = X(k, j) for k <= j < n, else 0.
+// Row-major, zero-padded image of the upper triangle of an n x n column-major
+// X (ldx): T[ldt k + j] = X(k, j) for k <= j < n, else 0, for k, j < ldt
+// (ldt = n rounded up to 256).
 __global__ __launch_bounds__(256) void k_upper_image(const double* __restrict__ X, int64_t ldx, int n,
-                                                     double* __restrict__ T) {
+                                                     double* __restrict__ T, int64_t ldt) {
   __shared__ double tile[32][33];
   const int bk = blockIdx.y * 32, bj = blockIdx.x * 32;  // T rows k, columns j
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
@@ -449,36 +607,39 @@ __global__ __launch_bounds__(256) void k_upper_image(const double* __restrict__ 
   }
   __syncthreads();
   for (int q = ty; q < 32; q += 8) {  // write T[k = bk + q][j = bj + tx]: coalesced along j
-    T[(int64_t)(bk + q) * kTallUld + bj + tx] = tile[tx][q];
+    T[(int64_t)(bk + q) * ldt + bj + tx] = tile[tx][q];
   }
 }
 
+int64_t upper_image_ld(int64_t n) { return (n + kTallUld - 1) / kTallUld * kTallUld; }
+
 hipError_t launch_upper_image(const double* X, int64_t ldx, int n, double* T, hipStream_t s) {
-  if (n > kTallUld) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_upper_image, dim3(kTallUld / 32, kTallUld / 32), dim3(256), 0, s, X, ldx, n, T);
+  const int64_t ld = upper_image_ld(n);
+  hipLaunchKernelGGL(k_upper_image, dim3((unsigned)(ld / 32), (unsigned)(ld / 32)), dim3(256), 0, s, X, ldx, n, T,
+                     ld);
   return hipGetLastError();
 }
 
 hipError_t launch_tall_gemm(int a_f32, const void* A, int64_t m, int n, int64_t lda, const double* Uimg, double* Q,
                             int64_t ldq, const int32_t* info, hipStream_t s) {
   if (m <= 0 || n <= 0) return hipSuccess;
-  if (n > kTallUld) return hipErrorInvalidValue;
-  dim3 grid((unsigned)((m + kTallRows - 1) / kTallRows));
+  const int64_t ld = upper_image_ld(n);
+  dim3 grid((unsigned)((m + kTallRows - 1) / kTallRows), (unsigned)(ld / kTallUld));
   if (a_f32)
-    hipLaunchKernelGGL((k_tall<float, false>), grid, dim3(512), 0, s, (const float*)A, m, n, lda, Uimg, (void*)Q,
-                       ldq, info);
+    hipLaunchKernelGGL((k_tall<float, false>), grid, dim3(512), 0, s, (const float*)A, m, n, lda, Uimg, ld,
+                       (void*)Q, ldq, info);
   else
-    hipLaunchKernelGGL((k_tall<double, false>), grid, dim3(512), 0, s, (const double*)A, m, n, lda, Uimg, (void*)Q,
-                       ldq, info);
+    hipLaunchKernelGGL((k_tall<double, false>), grid, dim3(512), 0, s, (const double*)A, m, n, lda, Uimg, ld,
+                       (void*)Q, ldq, info);
   return hipGetLastError();
 }
 
 hipError_t launch_tall_gemm_f32(const double* A, int64_t m, int n, int64_t lda, const double* Uimg, float* Q,
                                 int64_t ldq, const int32_t* info, hipStream_t s) {
   if (m <= 0 || n <= 0) return hipSuccess;
-  if (n > kTallUld) return hipErrorInvalidValue;
-  dim3 grid((unsigned)((m + kTallRows - 1) / kTallRows));
-  hipLaunchKernelGGL((k_tall<double, true>), grid, dim3(512), 0, s, A, m, n, lda, Uimg, (void*)Q, ldq, info);
+  const int64_t ld = upper_image_ld(n);
+  dim3 grid((unsigned)((m + kTallRows - 1) / kTallRows), (unsigned)(ld / kTallUld));
+  hipLaunchKernelGGL((k_tall<double, true>), grid, dim3(512), 0, s, A, m, n, lda, Uimg, ld, (void*)Q, ldq, info);
   return hipGetLastError();
 }
 
