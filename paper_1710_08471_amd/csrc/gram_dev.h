@@ -17,9 +17,7 @@ namespace cqr2 {
 // row0 + 4k + b: the four hardware blocks act as a 4-way split of the 16 rows.
 // The four partial sums are added (lanes l, l^4, l^8, l^12) once at the end.
 //
-// Work split inside a workgroup: the block-lower-triangle rows I = 0..NG-1
-// (row I has I+1 blocks) are dealt to waves in snake order, which gives every
-// wave the same number of MFMAs when NG is a multiple of 2*NW.
+// Work split inside a workgroup: see GramLayout.
 // ============================================================================
 constexpr int kStageRows = 64;  // rows of A per LDS stage (one 512-byte segment per column)
 
@@ -33,44 +31,83 @@ constexpr int kStageRows = 64;  // rows of A per LDS stage (one 512-byte segment
 __device__ __forceinline__ int stage_swz(int c) { return (0x18140C00u >> (8 * (c & 3))) & 0xff; }
 __device__ __forceinline__ int stage_pos(int c, int r) { return c * kStageRows + (r ^ stage_swz(c)); }
 
+// Which wave computes block (I, J), J <= I, of the lower block triangle.
+// Eight waves and NG >= 16: square patches of a 4 x 4 grid of super-blocks
+// (S = NG / 4 block rows each); the six off-diagonal patches go to waves 0..5,
+// the diagonal patches (0,0) + (3,3) to wave 6 and (1,1) + (2,2) to wave 7, so
+// a wave multiplies 2 S fragments per k-step (the two waves of a SIMD, w and
+// w + 4, carry 128 or 136 blocks together).  Otherwise: block rows dealt in
+// snake order, which balances the MFMAs when NG is a multiple of 2 NW.
 template <int NG, int NW>
 struct GramLayout {
+  static constexpr bool patches = NW == 8 && NG >= 16;
+  static constexpr int S = NG / 4;
   static constexpr int wave_of_row(int I) {
     const int P = 2 * NW;
     const int rr = I % P;
     return rr < NW ? rr : P - 1 - rr;
   }
-  static constexpr int blocks_of(int w) {
-    int c = 0;
-    for (int I = 0; I < NG; ++I)
-      if (wave_of_row(I) == w) c += I + 1;
-    return c;
+  static constexpr int patch_wave(int R, int C) {
+    if (R == C) return (R == 0 || R == 3) ? 6 : 7;
+    return R * (R - 1) / 2 + C;  // (1,0) 0, (2,0) 1, (2,1) 2, (3,0) 3, (3,1) 4, (3,2) 5
   }
-  static constexpr int max_row(int w) {
-    int mx = -1;
-    for (int I = 0; I < NG; ++I)
-      if (wave_of_row(I) == w) mx = I;
-    return mx;
-  }
+  static constexpr int wave_of_block(int I, int J) { return patches ? patch_wave(I / S, J / S) : wave_of_row(I); }
 };
 
 template <int NG, int NW, int W>
 struct WaveBlocks {
   using L = GramLayout<NG, NW>;
-  static constexpr int count = L::blocks_of(W);
+  static constexpr int count_blocks() {
+    int c = 0;
+    for (int I = 0; I < NG; ++I)
+      for (int J = 0; J <= I; ++J)
+        if (L::wave_of_block(I, J) == W) ++c;
+    return c;
+  }
+  static constexpr int count = count_blocks();
   static constexpr int cap = count > 0 ? count : 1;
+  // fragments (4-column groups) the wave reads per k-step
+  static constexpr int count_frags() {
+    int c = 0;
+    for (int g = 0; g < NG; ++g) {
+      bool used = false;
+      for (int I = 0; I < NG; ++I)
+        for (int J = 0; J <= I; ++J)
+          if (L::wave_of_block(I, J) == W && (I == g || J == g)) used = true;
+      c += used ? 1 : 0;
+    }
+    return c;
+  }
+  static constexpr int NFW = count_frags() > 0 ? count_frags() : 1;
   struct List {
     int I[cap];
     int J[cap];
+    int fi[cap];   // position of group I in FC
+    int fj[cap];   // position of group J in FC
+    int FC[NFW];   // the 4-column groups read, ascending
   };
   static constexpr List make() {
     List l{};
+    int pos[NG] = {};
+    int nf = 0;
+    for (int g = 0; g < NG; ++g) {
+      bool used = false;
+      for (int I = 0; I < NG; ++I)
+        for (int J = 0; J <= I; ++J)
+          if (L::wave_of_block(I, J) == W && (I == g || J == g)) used = true;
+      if (used) {
+        l.FC[nf] = g;
+        pos[g] = nf++;
+      }
+    }
     int k = 0;
     for (int I = 0; I < NG; ++I)
-      if (L::wave_of_row(I) == W)
-        for (int J = 0; J <= I; ++J) {
+      for (int J = 0; J <= I; ++J)
+        if (L::wave_of_block(I, J) == W) {
           l.I[k] = I;
           l.J[k] = J;
+          l.fi[k] = pos[I];
+          l.fj[k] = pos[J];
           ++k;
         }
     return l;
@@ -121,8 +158,6 @@ __device__ __forceinline__ void gram_wave_body(const double* __restrict__ A, int
                                                double* __restrict__ out) {
   using WB = WaveBlocks<NG, NW, W>;
   using ST = GramStage<NG, NW>;
-  constexpr int MR = GramLayout<NG, NW>::max_row(W);
-  constexpr int NF = MR >= 0 ? MR + 1 : 1;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
 
@@ -158,12 +193,12 @@ __device__ __forceinline__ void gram_wave_body(const double* __restrict__ A, int
 #pragma unroll 1
       for (int t = 0; t < kStageRows / 16; ++t) {
         const int r = 16 * t + frow;
-        double f[NF];
+        double f[WB::NFW];
 #pragma unroll
-        for (int c = 0; c < NF; ++c) f[c] = bcur[stage_pos(4 * c + fcol, r)];
+        for (int c = 0; c < WB::NFW; ++c) f[c] = bcur[stage_pos(4 * WB::list.FC[c] + fcol, r)];
 #pragma unroll
         for (int b = 0; b < WB::count; ++b)
-          acc[b] = __builtin_amdgcn_mfma_f64_4x4x4f64(f[WB::list.I[b]], f[WB::list.J[b]], acc[b], 0, 0, 0);
+          acc[b] = __builtin_amdgcn_mfma_f64_4x4x4f64(f[WB::list.fi[b]], f[WB::list.fj[b]], acc[b], 0, 0, 0);
       }
     }
     __builtin_amdgcn_s_waitcnt(0);
