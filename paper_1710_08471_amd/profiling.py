@@ -29,25 +29,39 @@ import re
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 
-# Source file that defines and launches each kernel family: a counter result
-# stays valid while that file is unchanged.
+# Source files that define and launch each kernel family (the .hip file and
+# the device headers it includes): a counter result stays valid while they are
+# unchanged.
 KERNEL_SOURCE = {
-    "k_gram_partials": "cqr2_gram.hip",
-    "k_gram_reduce": "cqr2_gram.hip",
-    "k_cholinv": "cqr2_cholinv.hip",
-    "k_apply_rinv": "cqr2_apply.hip",
-    "k_gemm": "cqr2_gemm.hip",
-    "k_gemm_f32": "cqr2_gemm.hip",
-    "k_gemm_reduce": "cqr2_gemm.hip",
+    "k_gram_partials": ["cqr2_gram.hip", "gram_dev.h"],
+    "k_gram_reduce": ["cqr2_gram.hip", "gram_dev.h"],
+    "k_cholinv": ["cqr2_cholinv.hip", "cholinv_dev.h"],
+    "k_apply_rinv": ["cqr2_apply.hip", "apply_dev.h"],
+    "k_gemm": ["cqr2_gemm.hip"],
+    "k_gemm_f32": ["cqr2_gemm.hip"],
+    "k_gemm_reduce": ["cqr2_gemm.hip"],
+    "k_gram_wide": ["cqr2_wide.hip", "sync_dev.h"],
+    "k_gram_wide_reduce": ["cqr2_wide.hip", "sync_dev.h"],
+    "k_syrk_tile": ["cqr2_wide.hip", "sync_dev.h"],
+    "k_syrk_reduce": ["cqr2_wide.hip", "sync_dev.h"],
+    "k_tall": ["cqr2_wide.hip", "sync_dev.h"],
+    "k_upper_image": ["cqr2_wide.hip", "sync_dev.h"],
+    "k_step": ["cqr2_step.hip", "gram_dev.h", "cholinv_dev.h", "apply_dev.h"],
 }
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
 
+def kernel_sources(kernel: str):
+    return KERNEL_SOURCE.get(kernel, ["cqr2_driver.hip"])
+
+
 def source_sha(kernel: str) -> str:
-    """Short hash of the source file of `kernel` (cqr2_driver.hip if unlisted)."""
-    path = os.path.join(PKG, "csrc", KERNEL_SOURCE.get(kernel, "cqr2_driver.hip"))
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Short hash of the source files of `kernel` (cqr2_driver.hip if unlisted)."""
+    h = hashlib.sha256()
+    for name in kernel_sources(kernel):
+        with open(os.path.join(PKG, "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def short_name(name: str) -> str:
@@ -129,7 +143,7 @@ def traffic_report(fetch_dir: str, write_dir: str, copy_bytes: int, cmd_fetch: s
         wr = write[name][0] * 1024.0 * w_scale
         kernels[fam] = {"name": name, "dispatches": fetch[name][1], "read_bytes_per_launch": rd,
                         "write_bytes_per_launch": wr, "bytes_per_launch": rd + wr,
-                        "source": KERNEL_SOURCE.get(fam, "cqr2_driver.hip"), "source_sha": source_sha(fam)}
+                        "source": "+".join(kernel_sources(fam)), "source_sha": source_sha(fam)}
     data = {
         "calibration": {"copy_bytes": copy_bytes, "fetch_kib": copy_f[0], "write_kib": copy_w[0],
                         "fetch_scale": f_scale, "write_scale": w_scale},
