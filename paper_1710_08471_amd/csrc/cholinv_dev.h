@@ -21,6 +21,29 @@ namespace cqr2 {
 // columns publish them to a double-buffered LDS panel, every thread forms the
 // L and Y entries it needs from it and applies the rank-B updates.
 // ============================================================================
+// s = sqrt(d) and y = 1/sqrt(d) for d > 0, each within a few ulp: the
+// hardware reciprocal square root as a seed, two steps of the coupled
+// (Goldschmidt) iteration for sqrt(d) and 1/(2 sqrt(d)), then one Newton
+// correction of the square root.  Inputs below 2^-960 are scaled by an exact
+// power of two first.  A much shorter dependency chain than sqrt() followed
+// by a correctly rounded division.
+__device__ __forceinline__ void sqrt_rsqrt(double d, double& s, double& y) {
+  const bool tiny = d < 0x1p-960;
+  const double ds = tiny ? d * 0x1p+960 : d;
+  const double y0 = __builtin_amdgcn_rsq(ds);
+  double g = ds * y0, h = 0.5 * y0;
+  double e = fma(-g, h, 0.5);
+  g = fma(g, e, g);
+  h = fma(h, e, h);
+  e = fma(-g, h, 0.5);
+  g = fma(g, e, g);
+  h = fma(h, e, h);
+  const double rr = fma(-g, g, ds);
+  g = fma(rr, h, g);
+  s = tiny ? g * 0x1p-480 : g;
+  y = tiny ? (2.0 * h) * 0x1p+480 : 2.0 * h;
+}
+
 // Input of the factorization: the lower triangle of W (n x n, ldw), or -- when
 // `part` is set -- the sum, in split order, of `splits` partial Grams laid
 // out as the Gram kernel writes them (per split: lower 4x4 blocks (I, J),
@@ -114,8 +137,7 @@ __device__ __forceinline__ void cholinv_body(const CholInvSrc& src, int n, doubl
 #pragma unroll
           for (int ii = 0; ii < jj; ++ii) d = fma(-Lb[jj][ii], Lb[jj][ii], d);
           if (!(d > 0.0) && bad == 0) bad = j0 + jj + 1;  // non-positive or NaN pivot (uniform)
-          sd[jj] = sqrt(d);
-          y[jj] = 1.0 / sd[jj];
+          sqrt_rsqrt(d, sd[jj], y[jj]);
           Lb[jj][jj] = sd[jj];
 #pragma unroll
           for (int kk = jj + 1; kk < B; ++kk) {
