@@ -150,7 +150,13 @@ def serve_stream(cq, torch, count: int, rate: float, seed: int):
     log(f"serving: {count} requests generated on the device in {time.perf_counter() - t0:.1f} s "
         f"({total_a / 1e9:.1f} GB of A)")
 
-    def run(arrivals_ms):
+    # least-squares requests for the mixed-type run: every 4th request, nrhs 1..8
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed + 1)
+    lsq = {r.idx: (torch.randn((1 + r.idx % 8, r.m), generator=gen, device=dev, dtype=torch.float64).t(),
+                   cq.empty_colmajor(r.n, 1 + r.idx % 8, device=dev)) for r in reqs if r.idx % 4 == 0}
+
+    def run(arrivals_ms, with_lstsq=False):
         done = {}
         steps = 0
         with cq.Server(SERVE_ARENA, SERVE_BUDGET, SERVE_SLOTS) as sv:
@@ -160,7 +166,10 @@ def serve_stream(cq, torch, count: int, rate: float, seed: int):
             while len(done) < count:
                 now = (time.perf_counter() - h0) * 1e3
                 while i < count and arrivals_ms[i] <= now:
-                    sv.submit(i, mats[i], qs[i], rs[i])
+                    if with_lstsq and i in lsq:
+                        sv.submit_lstsq(i, mats[i], lsq[i][0], lsq[i][1], qs[i], rs[i])
+                    else:
+                        sv.submit(i, mats[i], qs[i], rs[i])
                     i += 1
                 sv.step()
                 steps += 1
@@ -183,7 +192,13 @@ def serve_stream(cq, torch, count: int, rate: float, seed: int):
     high["rate_per_s"] = hi_rate
     log(f"serving open loop at {hi_rate:.0f}/s: {high}")
 
-    # oracle check on the first request of every n in the mix
+    # mixed request types: a quarter of the stream are least-squares solves
+    mixed = run([r.arrival_s * 1e3 for r in reqs], with_lstsq=True)
+    mixed["lstsq_requests"] = len(lsq)
+    log(f"serving open loop at {rate:.0f}/s, 1 in 4 requests least squares: {mixed}")
+
+    # oracle check on the first request of every n in the mix (the last run
+    # served the least-squares requests: their X is checked too)
     checked = []
     for nn in sorted({r.n for r in reqs}):
         k = next(r.idx for r in reqs if r.n == nn)
@@ -193,11 +208,22 @@ def serve_stream(cq, torch, count: int, rate: float, seed: int):
         ok = (oracle.orthogonality(q) <= 1e-12 and oracle.residual(a, q, r_) <= 1e-13
               and oracle.rel_fro(r_, r_ref) <= 1e-9)
         checked.append({"request": k, "m": reqs[k].m, "n": nn, "ok": bool(ok)})
+    for nn in sorted({r.n for r in reqs}):
+        k = next((r.idx for r in reqs if r.n == nn and r.idx in lsq), None)
+        if k is None:
+            continue
+        a = mats[k].cpu().numpy()
+        b = lsq[k][0].cpu().numpy()
+        x_ref, _, _ = oracle.lstsq(a, b)
+        x = lsq[k][1].cpu().numpy()
+        ok = np.linalg.norm(x - x_ref) <= 1e-12 * max(reqs[k].kappa, 10.0) * np.linalg.norm(x_ref)
+        checked.append({"request": k, "m": reqs[k].m, "n": nn, "lstsq_nrhs": b.shape[1], "ok": bool(ok)})
     return {
         "requests": count, "rate_per_s": rate, "seed": seed,
         "mix": "m log-uniform [1024,131072], n in {16,32,64,128,256}, kappa log-uniform [1e1,1e6]",
         "solves_per_s": opened["solves_per_s"], "p50_ms": opened["p50_ms"], "p99_ms": opened["p99_ms"],
-        "closed_loop": closed, "open_loop": opened, "open_loop_0.8C": high, "oracle_sample": checked,
+        "closed_loop": closed, "open_loop": opened, "open_loop_0.8C": high, "open_loop_lstsq_mix": mixed,
+        "oracle_sample": checked,
         "slots": SERVE_SLOTS, "arena_bytes": SERVE_ARENA, "footprint_budget": SERVE_BUDGET,
     }
 

@@ -231,6 +231,17 @@ int cqr2_server_destroy(cqr2_server* s);
  * is rejected: nothing to do), or CQR2_ERR_TOO_LARGE if it could never be
  * admitted (workspace above the arena or footprint above the budget). */
 int cqr2_server_submit(cqr2_server* s, const cqr2_problem* p, int64_t tag);
+/* Queue a least-squares request: the factorization of p (into p->Q, p->R, as
+ * cqr2_server_submit) followed, on the GPU, by X = R^{-1} (Qᵀ B) through the
+ * two passes' triangular inverses -- what cqr2_lstsq computes, as one served
+ * request.  B: m x nrhs (ldb >= m), read only, may alias A; X: n x nrhs
+ * (ldx >= n), NaN after a breakdown.  B and X stay owned by the caller until
+ * the request is reported done.  Returns 0, -1 (server), -2 (invalid problem
+ * or n == 0), -3 (B null, misaligned or overlapping Q or R), -4 (ldb), -5
+ * (nrhs < 1), -6 (X null, misaligned or overlapping A, B, Q or R), -7 (ldx),
+ * or CQR2_ERR_TOO_LARGE. */
+int cqr2_server_submit_lstsq(cqr2_server* s, const cqr2_problem* p, const double* B, int64_t ldb, int64_t nrhs,
+                             double* X, int64_t ldx, int64_t tag);
 /* Admit and launch one step.  n_active / n_queued (may be NULL): requests in
  * flight and waiting after the step. */
 int cqr2_server_step(cqr2_server* s, int32_t* n_active, int32_t* n_queued);

@@ -50,6 +50,7 @@ SIGNATURES = {
     "cqr2_server_create": (_i32, [_sz, _sz, _i32, _vp, ctypes.POINTER(_vp)]),
     "cqr2_server_destroy": (_i32, [_vp]),
     "cqr2_server_submit": (_i32, [_vp, _vp, _i64]),
+    "cqr2_server_submit_lstsq": (_i32, [_vp, _vp, _vp, _i64, _i64, _vp, _i64, _i64]),
     "cqr2_server_step": (_i32, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "cqr2_server_poll": (_i32, [_vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double), _i32,
                                 ctypes.POINTER(ctypes.c_int32)]),
@@ -345,6 +346,16 @@ class Server:
         p = problem(A, Q, R, info)
         _check(self._lib.cqr2_server_submit(self._h, ctypes.byref(p), tag), "cqr2_server_submit")
         self._keep[tag] = (A, Q, R, info)   # tensors stay alive until done
+
+    def submit_lstsq(self, tag: int, A, B, X, Q, R, info=None):
+        """Queue a least-squares request: A = QR into Q, R and X = R^-1 Qᵀ B."""
+        p = problem(A, Q, R, info)
+        if B.dim() == 1 or X.dim() == 1:
+            raise ValueError("B and X must be 2-D (column-major views)")
+        nrhs = B.shape[1]
+        _check(self._lib.cqr2_server_submit_lstsq(self._h, ctypes.byref(p), _ptr(B), _ld(B), nrhs, _ptr(X), _ld(X),
+                                                  tag), "cqr2_server_submit_lstsq")
+        self._keep[tag] = (A, B, X, Q, R, info)
 
     def step(self):
         act, q = ctypes.c_int32(), ctypes.c_int32()

@@ -234,27 +234,14 @@ int run_factor(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, in
 // ---- least squares ------------------------------------------------------------
 namespace {
 struct LstsqLayout {
-  size_t off_c = 0, off_t = 0, off_part = 0, total = 0;
-  int splits = 1;
+  size_t off_tail = 0, total = 0;
 };
 
 LstsqLayout lstsq_layout(int64_t m, int64_t n, int64_t nrhs) {
   LstsqLayout L;
-  size_t off = align_up(factor_workspace(m, n, CQR2_FP64));
-  const size_t cb = align_up((size_t)n * nrhs * sizeof(double));
-  L.off_c = off; off += cb;
-  L.off_t = off; off += cb;
-  L.splits = cqr2::gemm_pick_splits(n, nrhs, m, cqr2::kPlanCUs);
-  L.off_part = off; off += align_up(cqr2::gemm_workspace_bytes(n, nrhs, L.splits));
-  L.total = off;
+  L.off_tail = align_up(factor_workspace(m, n, CQR2_FP64));
+  L.total = L.off_tail + align_up(cqr2::lstsq_tail_bytes(m, n, nrhs));
   return L;
-}
-
-// X = NaN after a breakdown (the solve's products skip their work then).
-__global__ void k_nan_if_info(double* X, int64_t ldx, int64_t rows, int64_t cols, const int32_t* info) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= rows * cols || *info == 0) return;
-  X[(e % rows) + (e / rows) * ldx] = __builtin_nan("");
 }
 }  // namespace
 
@@ -387,33 +374,16 @@ int cqr2_lstsq(const double* A, int64_t m, int64_t n, int64_t lda, const double*
   const int rc = run_factor(A, m, n, lda, Q, ldq, R, ldr, ws, d_info, CQR2_FP64, s);
   if (rc != 0 || nrhs == 0) return rc;
   const int32_t* info = (const int32_t*)ws;  // both layouts keep the info word first
-  double* C = (double*)(ws + L.off_c);
-  double* T = (double*)(ws + L.off_t);
-  // C = Qᵀ B
-  CQR2_TRY(cqr2::launch_gemm(1, 0, n, nrhs, m, 1.0, Q, ldq, B, ldb, 0.0, C, n, 0, L.splits,
-                             (double*)(ws + L.off_part), info, s));
-  // T = R2^{-1} C, X = R1^{-1} T
+  char* tail = ws + L.off_tail;
   if (use_small(n, CQR2_FP64)) {
-    // row-major U images: U[i np + k] = R^{-1}(i, k), i.e. op(A) = Aᵀ of a column-major np x np view
+    // row-major U images: U[i np + k] = R^{-1}(i, k), i.e. op(U) = Uᵀ of a column-major np x np view
     const SmallLayout SL = make_small_layout(m, n);
-    const double* U1 = (const double*)(ws + SL.off_u1);
-    const double* U2 = (const double*)(ws + SL.off_u2);
-    CQR2_TRY(cqr2::launch_gemm(1, 0, n, nrhs, n, 1.0, U2, SL.np, C, n, 0.0, T, n, cqr2::GEMM_A_UPPER, 1, nullptr,
-                               info, s));
-    CQR2_TRY(cqr2::launch_gemm(1, 0, n, nrhs, n, 1.0, U1, SL.np, T, n, 0.0, X, ldx, cqr2::GEMM_A_UPPER, 1, nullptr,
-                               info, s));
-  } else {
-    const cqr2::GeneralPlan p = cqr2::plan_general(m, n, false);
-    const double* Ri1 = (const double*)(ws + p.off_ri1);
-    const double* Ri2 = (const double*)(ws + p.off_ri2);
-    CQR2_TRY(cqr2::launch_gemm(0, 0, n, nrhs, n, 1.0, Ri2, n, C, n, 0.0, T, n, cqr2::GEMM_A_UPPER, 1, nullptr, info,
-                               s));
-    CQR2_TRY(cqr2::launch_gemm(0, 0, n, nrhs, n, 1.0, Ri1, n, T, n, 0.0, X, ldx, cqr2::GEMM_A_UPPER, 1, nullptr,
-                               info, s));
+    return check_hip(cqr2::lstsq_tail(Q, ldq, B, ldb, m, n, nrhs, (const double*)(ws + SL.off_u1),
+                                      (const double*)(ws + SL.off_u2), SL.np, 1, X, ldx, tail, info, s));
   }
-  const int64_t total = n * nrhs;
-  hipLaunchKernelGGL(k_nan_if_info, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, X, ldx, n, nrhs, info);
-  return check_hip(hipGetLastError());
+  const cqr2::GeneralPlan p = cqr2::plan_general(m, n, false);
+  return check_hip(cqr2::lstsq_tail(Q, ldq, B, ldb, m, n, nrhs, (const double*)(ws + p.off_ri1),
+                                    (const double*)(ws + p.off_ri2), n, 0, X, ldx, tail, info, s));
 }
 
 size_t cqr2_gram_workspace_size(int64_t m, int64_t n) {

@@ -1,6 +1,7 @@
 // Device-side drivers built from the kernels: the recursive CholInv of
-// Algorithm 2 for any n (base case: the single-workgroup kernel for n <= 128)
-// and CholeskyQR2 (Algorithms 4 and 5) for n > 128 on the general GEMM.
+// Algorithm 2 for any n (base case: the single-workgroup kernel for n <= 128),
+// CholeskyQR2 (Algorithms 4 and 5) for n > 128 on the general GEMM, and the
+// least-squares solve on a finished factorization.
 // Everything is enqueued on one stream; nothing synchronizes with the host.
 #include "cqr2_internal.h"
 
@@ -284,6 +285,47 @@ hipError_t factor_general(const double* A, int64_t m, int64_t n, int64_t lda, do
   CQR2_HIP(launch_finalize_r(W, n, R, ldr, n, info, d_info, s));
   th.end(5, s);
   return hipSuccess;
+}
+
+// ---- least squares on a finished factorization --------------------------------
+// The use of QR named in the paper's introduction: X = argmin ||A X - B|| is
+// R^{-1} Qᵀ B, with R^{-1} = R1^{-1} R2^{-1} from the two passes' inverses.
+namespace {
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+// X = NaN after a breakdown (the products skip their work then).
+__global__ void k_nan_if_info(double* X, int64_t ldx, int64_t rows, int64_t cols, const int32_t* info) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * cols || *info == 0) return;
+  X[(e % rows) + (e / rows) * ldx] = __builtin_nan("");
+}
+}  // namespace
+
+size_t lstsq_tail_bytes(int64_t m, int64_t n, int64_t nrhs) {
+  const size_t cb = align256((size_t)n * nrhs * sizeof(double));
+  const int splits = gemm_pick_splits(n, nrhs, m, kPlanCUs);
+  return 2 * cb + align256(gemm_workspace_bytes(n, nrhs, splits));
+}
+
+hipError_t lstsq_tail(const double* Q, int64_t ldq, const double* B, int64_t ldb, int64_t m, int64_t n,
+                      int64_t nrhs, const double* U1, const double* U2, int64_t ldu, int utrans, double* X,
+                      int64_t ldx, char* work, const int32_t* info, hipStream_t s) {
+  const size_t cb = align256((size_t)n * nrhs * sizeof(double));
+  double* C = (double*)work;
+  double* T = (double*)(work + cb);
+  double* part = (double*)(work + 2 * cb);
+  const int splits = gemm_pick_splits(n, nrhs, m, kPlanCUs);
+  // C = Qᵀ B (split over the m rows, fixed-order reduction)
+  hipError_t e = launch_gemm(1, 0, n, nrhs, m, 1.0, Q, ldq, B, ldb, 0.0, C, n, 0, splits, part, info, s);
+  if (e != hipSuccess) return e;
+  // T = R2^{-1} C, X = R1^{-1} T
+  e = launch_gemm(utrans, 0, n, nrhs, n, 1.0, U2, ldu, C, n, 0.0, T, n, GEMM_A_UPPER, 1, nullptr, info, s);
+  if (e != hipSuccess) return e;
+  e = launch_gemm(utrans, 0, n, nrhs, n, 1.0, U1, ldu, T, n, 0.0, X, ldx, GEMM_A_UPPER, 1, nullptr, info, s);
+  if (e != hipSuccess) return e;
+  const int64_t total = n * nrhs;
+  hipLaunchKernelGGL(k_nan_if_info, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, X, ldx, n, nrhs, info);
+  return hipGetLastError();
 }
 
 }  // namespace cqr2

@@ -186,6 +186,17 @@ StepLayout step_layout(int64_t m, int64_t n);
 int step_workgroups(int64_t m, int phase);
 hipError_t launch_step(const StepTask* d_tasks, int ntasks, int total_wgs, hipStream_t s);
 
+// ---- least squares on a finished factorization ---------------------------
+// X = R1^{-1} R2^{-1} Qᵀ B (n x nrhs, ldx).  U1, U2 hold R1^{-1}, R2^{-1} as
+// op(U) with leading dimension ldu: utrans = 1 for the row-major padded images
+// of the n <= 128 paths, 0 for the column-major inverses of the tiled path.
+// work: lstsq_tail_bytes(m, n, nrhs), 256-byte aligned.  X is NaN when *info
+// is nonzero.
+size_t lstsq_tail_bytes(int64_t m, int64_t n, int64_t nrhs);
+hipError_t lstsq_tail(const double* Q, int64_t ldq, const double* B, int64_t ldb, int64_t m, int64_t n,
+                      int64_t nrhs, const double* U1, const double* U2, int64_t ldu, int utrans, double* X,
+                      int64_t ldx, char* work, const int32_t* info, hipStream_t s);
+
 // ---- small helpers ---------------------------------------------------------
 hipError_t launch_set_info(int32_t* info, int32_t value, hipStream_t s);
 

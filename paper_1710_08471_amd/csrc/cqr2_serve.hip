@@ -1,6 +1,8 @@
 // Many CholeskyQR2 problems per launch: the batched entry point and the
 // continuous-batching server (host side).  Both drive the multi-problem step
-// kernel (cqr2_step.hip) for n <= 128 and the tiled path for larger n.
+// kernel (cqr2_step.hip) for n <= 128 and the tiled path for larger n.  Server
+// requests are QR factorizations or least-squares solves (the factorization
+// followed by X = R^{-1} Qᵀ B).
 //
 // Task tables travel host -> device through a ring of pinned host buffers;
 // a buffer is rewritten only after the copy that last read it has completed
@@ -170,6 +172,12 @@ struct cqr2_server {
     int64_t tag;
     size_t ws_bytes, footprint;
     bool large;
+    // least-squares requests (nrhs > 0): B (m x nrhs), X (n x nrhs); the
+    // solve's workspace follows the factorization's at tail_off
+    int64_t nrhs = 0, ldb = 0, ldx = 0;
+    const double* B = nullptr;
+    double* X = nullptr;
+    size_t tail_off = 0;
   };
   struct Active {
     Req r;
@@ -251,9 +259,16 @@ struct cqr2_server {
         const cqr2::GeneralPlan plan = cqr2::plan_general(p.m, p.n, false);
         hipStream_t ls = large[large_next];
         large_next = (large_next + 1) % kLargeStreams;
-        hipError_t e = cqr2::factor_general(p.A, p.m, p.n, p.lda, p.Q, p.ldq, p.R, p.ldr, arena_base + off, plan,
-                                            false, p.d_info, ls, cqr2::TimerHook{});
+        char* ws = arena_base + off;
+        hipError_t e = cqr2::factor_general(p.A, p.m, p.n, p.lda, p.Q, p.ldq, p.R, p.ldr, ws, plan, false,
+                                            p.d_info, ls, cqr2::TimerHook{});
         if (e != hipSuccess) return CQR2_ERR_HIP;
+        if (r.nrhs > 0) {
+          e = cqr2::lstsq_tail(p.Q, p.ldq, r.B, r.ldb, p.m, p.n, r.nrhs, (const double*)(ws + plan.off_ri1),
+                               (const double*)(ws + plan.off_ri2), p.n, 0, r.X, r.ldx, ws + r.tail_off,
+                               (const int32_t*)(ws + plan.off_info), ls);
+          if (e != hipSuccess) return CQR2_ERR_HIP;
+        }
         hipEvent_t ev = get_event();
         if (ev == nullptr || hipEventRecord(ev, ls) != hipSuccess) return CQR2_ERR_HIP;
         ++n_large_running;
@@ -283,6 +298,17 @@ struct cqr2_server {
     if (rc) return rc;
     rc = to_code(cqr2::launch_step((const cqr2::StepTask*)dtab, (int)table.size(), wg, stream));
     if (rc) return rc;
+    // least-squares requests whose factorization this step completes: the solve
+    for (const Active& a : active) {
+      if (a.phase != cqr2::kStepPhases - 1 || a.r.nrhs == 0) continue;
+      const cqr2_problem& p = a.r.p;
+      const cqr2::StepLayout L = cqr2::step_layout(p.m, p.n);
+      char* ws = arena_base + a.ws_off;
+      rc = to_code(cqr2::lstsq_tail(p.Q, p.ldq, a.r.B, a.r.ldb, p.m, p.n, a.r.nrhs, (const double*)(ws + L.off_u1),
+                                    (const double*)(ws + L.off_u2), L.np, 1, a.r.X, a.r.ldx, ws + a.r.tail_off,
+                                    (const int32_t*)(ws + L.off_info), stream));
+      if (rc) return rc;
+    }
     hipEvent_t ev = get_event();
     if (ev == nullptr || hipEventRecord(ev, stream) != hipSuccess) return CQR2_ERR_HIP;
     Finishing fin{ev, {}, {}};
@@ -437,6 +463,40 @@ int cqr2_server_submit(cqr2_server* s, const cqr2_problem* p, int64_t tag) {
   if (p == nullptr || cqr2_problem_check(p) != 0) return -2;
   if (p->n == 0) return -3;
   cqr2_server::Req r{*p, tag, problem_workspace(*p), problem_footprint(*p), p->n > kStepMaxN};
+  if (r.ws_bytes > s->arena.size() || (s->budget && r.footprint > s->budget)) return CQR2_ERR_TOO_LARGE;
+  s->queue.push_back(r);
+  return 0;
+}
+
+int cqr2_server_submit_lstsq(cqr2_server* s, const cqr2_problem* p, const double* B, int64_t ldb, int64_t nrhs,
+                             double* X, int64_t ldx, int64_t tag) {
+  if (s == nullptr) return -1;
+  if (p == nullptr || cqr2_problem_check(p) != 0) return -2;
+  if (p->n == 0) return -2;
+  const int64_t m = p->m, n = p->n;
+  if (nrhs < 1) return -5;
+  if (ldb < (m > 1 ? m : 1)) return -4;
+  if (ldx < (n > 1 ? n : 1)) return -7;
+  if (B == nullptr || ((uintptr_t)B & 7u) != 0) return -3;
+  if (X == nullptr || ((uintptr_t)X & 7u) != 0) return -6;
+  const size_t bb = mat_bytes(m, nrhs, ldb), xb = mat_bytes(n, nrhs, ldx);
+  const size_t ab = mat_bytes(m, n, p->lda), qb = mat_bytes(m, n, p->ldq), rb = mat_bytes(n, n, p->ldr);
+  auto overlap = [](const void* a, size_t na, const void* b, size_t nb) {
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return na && nb && x < y + nb && y < x + na;
+  };
+  if (overlap(B, bb, p->Q, qb) || overlap(B, bb, p->R, rb)) return -3;
+  if (overlap(X, xb, p->A, ab) || overlap(X, xb, p->Q, qb) || overlap(X, xb, p->R, rb) || overlap(X, xb, B, bb))
+    return -6;
+  const size_t fws = problem_workspace(*p);
+  const size_t tail = align_up(cqr2::lstsq_tail_bytes(m, n, nrhs));
+  cqr2_server::Req r{*p, tag, fws + tail, problem_footprint(*p) + bb + xb + tail, n > kStepMaxN};
+  r.nrhs = nrhs;
+  r.B = B;
+  r.ldb = ldb;
+  r.X = X;
+  r.ldx = ldx;
+  r.tail_off = fws;
   if (r.ws_bytes > s->arena.size() || (s->budget && r.footprint > s->budget)) return CQR2_ERR_TOO_LARGE;
   s->queue.push_back(r);
   return 0;
