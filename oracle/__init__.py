@@ -7,7 +7,11 @@ code with the HIP kernels or their host runtime.
 from .cqr2_ref import (  # noqa: F401
     NotSPD,
     cholinv,
+    cholinv_partial,
     cqr,
+    cqr_partial,
+    cqr2_partial,
+    solve_right_lt,
     cqr2,
     cqr2_mixed,
     cholesky_shift,

@@ -33,6 +33,18 @@ one CholeskyQR of A with W + s I in place of W, s = 11 (m n + n (n + 1)) u
 ||A||_F^2 (u = 2^-53, ||A||_F^2 = trace W), followed by CholeskyQR2 of the
 result; R = R3 R2 R1.  Parity of this form is pinned to Householder QR, closed
 forms and exact scaling, not to anything the paper prints.
+
+Partial inverse (``cholinv_partial``, ``cqr2_partial``): the alternative the
+paper describes for its 3D-CQR2 (Section "Communication-avoiding
+CholeskyQR2"): only triangular diagonal blocks of dimension n_o are inverted
+and Q is found by several matrix multiplications instead of one with the full
+R^{-1}; its experiments tune the recursion level down to which the inverse
+is formed (InverseDepth).  Reading taken: with depth d, the top d levels of
+Algorithm 2's recursion do not form Y21 (the inverse stays block diagonal
+with the blocks of level d), and every product that needs the inverse of such
+a block -- L21 = A21 L11^{-T} inside the recursion and Q = A R^{-1} -- is
+formed by block substitution over the inverted diagonal blocks, one matrix
+multiplication pair per block.  d = 0 is Algorithm 2 itself.
 """
 from __future__ import annotations
 
@@ -226,3 +238,73 @@ def lstsq(a: np.ndarray, b: np.ndarray):
     c = q.T @ b
     x = it["R1inv"] @ (it["R2inv"] @ c)
     return x, q, r
+
+
+def solve_right_lt(b: np.ndarray, l: np.ndarray, y: np.ndarray, blocks) -> np.ndarray:
+    """X = B L^{-T} by block substitution (X Lᵀ = B, L lower triangular).
+
+    ``y`` holds the inverses of L's diagonal blocks ``blocks`` (a list of
+    (start, stop) column ranges covering 0..n in order); nothing else of y is
+    read.  Block j: X_j = (B_j - X_{<j} L_{j,<j}ᵀ) Y_jjᵀ.
+    """
+    b = np.asarray(b, dtype=np.float64)
+    x = np.zeros_like(b)
+    for c0, c1 in blocks:
+        t = b[:, c0:c1] - x[:, :c0] @ l[c0:c1, :c0].T
+        x[:, c0:c1] = t @ y[c0:c1, c0:c1].T
+    return x
+
+
+def cholinv_partial(a: np.ndarray, depth: int):
+    """[L, Y, blocks] = CholInv with the inverse formed only below ``depth``.
+
+    At a level with depth > 0: L11, Y11 = CholInv_partial(A11, depth - 1);
+    L21 = A21 L11^{-T} by block substitution over Y11's diagonal blocks;
+    L22, Y22 = CholInv_partial(A22 - L21 L21ᵀ, depth - 1); Y21 is not formed
+    (zero).  depth == 0 (or n == 1) is Algorithm 2 (``cholinv``).  ``blocks``
+    lists the diagonal blocks of Y that are inverses of L's.
+    """
+    a = np.asarray(a, dtype=np.float64)
+    n = a.shape[0]
+    if depth <= 0 or n <= 1:
+        l, y = cholinv(a)
+        return l, y, [(0, n)]
+    h = n // 2
+    l11, y11, b11 = cholinv_partial(a[:h, :h], depth - 1)
+    l21 = solve_right_lt(a[h:, :h], l11, y11, b11)
+    schur = a[h:, h:] - l21 @ l21.T
+    try:
+        l22, y22, b22 = cholinv_partial(schur, depth - 1)
+    except NotSPD as e:
+        raise NotSPD(e.j + h) from None
+    l = np.zeros((n, n))
+    y = np.zeros((n, n))
+    l[:h, :h] = l11
+    l[h:, :h] = l21
+    l[h:, h:] = l22
+    y[:h, :h] = y11
+    y[h:, h:] = y22
+    return l, y, b11 + [(h + c0, h + c1) for c0, c1 in b22]
+
+
+def cqr_partial(a: np.ndarray, depth: int):
+    """CQR (Algorithm 4) with the partial inverse: W = Syrk(A);
+    L, Y, blocks = CholInv_partial(W, depth); R = Lᵀ; Q = A R^{-1} = A L^{-T}
+    by block substitution.  Returns (Q, R, Y, blocks)."""
+    a = np.asarray(a, dtype=np.float64)
+    w = syrk(a)
+    l, y, blocks = cholinv_partial(w, depth)
+    q = solve_right_lt(a, l, y, blocks)
+    return q, l.T.copy(), y, blocks
+
+
+def cqr2_partial(a: np.ndarray, depth: int):
+    """CQR2 (Algorithm 5) on ``cqr_partial``: returns (Q, R)."""
+    a = np.asarray(a, dtype=np.float64)
+    n = a.shape[1]
+    q1, r1, _, _ = cqr_partial(a, depth)
+    try:
+        q, r2, _, _ = cqr_partial(q1, depth)
+    except NotSPD as e:
+        raise NotSPD(n + e.j) from None
+    return q, upper_product(r2, r1)

@@ -384,3 +384,107 @@ def test_lstsq_exact_consistent_system():
     xt = np.arange(1.0, 9.0)[:, None]
     x, q, r = oracle.lstsq(h, h @ xt)
     assert np.array_equal(x, xt)
+
+
+# ---- partial inverse (InverseDepth): inverted diagonal blocks + block substitution ----
+
+@pytest.mark.parametrize("n", [5, 8, 13, 16, 33])
+@pytest.mark.parametrize("depth", [1, 2, 3])
+def test_cholinv_partial_exact_examples(n, depth):
+    """On the exact examples every FP64 step is exact, so L must equal the
+    exact L bit for bit and every inverted diagonal block must equal the same
+    block of the exact L^{-1} (a diagonal block of the inverse of a triangular
+    matrix is the inverse of its diagonal block); Y is zero elsewhere."""
+    d = _gold(f"cholinv_exact_n{n}.json")
+    l, y, blocks = oracle.cholinv_partial(np.array(d["W"]), depth)
+    assert np.array_equal(l, np.array(d["L"]))
+    y_ex = np.array(d["Y"])
+    mask = np.zeros((n, n), dtype=bool)
+    assert blocks[0][0] == 0 and blocks[-1][1] == n
+    assert all(b0[1] == b1[0] for b0, b1 in zip(blocks, blocks[1:]))
+    assert len(blocks) == min(2 ** depth, n) or n < 2 ** depth
+    for c0, c1 in blocks:
+        assert np.array_equal(y[c0:c1, c0:c1], y_ex[c0:c1, c0:c1])
+        mask[c0:c1, c0:c1] = True
+    assert np.all(y[~mask] == 0.0)
+
+
+@pytest.mark.parametrize("m,n,k", [(50, 7, 3), (300, 40, 5)])
+def test_solve_right_lt_matches_lapack_trsm(m, n, k):
+    """X = B L^{-T} by block substitution against LAPACK's triangular solve."""
+    rng = np.random.default_rng(11)
+    l = np.tril(rng.standard_normal((n, n))) + 4.0 * np.eye(n)
+    blocks = [(0, 2), (2, 3), (3, n // 2), (n // 2, n)]
+    y = np.zeros((n, n))
+    for c0, c1 in blocks:
+        y[c0:c1, c0:c1] = scipy.linalg.solve_triangular(l[c0:c1, c0:c1], np.eye(c1 - c0), lower=True)
+    b = rng.standard_normal((m, n))
+    x = oracle.solve_right_lt(b, l, y, blocks)
+    x_ref = scipy.linalg.solve_triangular(l, b.T, lower=True).T
+    assert np.linalg.norm(x - x_ref) <= 1e-13 * np.linalg.norm(x_ref)
+
+
+def test_cqr2_partial_depth0_is_cqr2():
+    a = gdv_matrix(500, 21, 1e4, 12)
+    q0, r0 = oracle.cqr2(a)
+    q, r = oracle.cqr2_partial(a, 0)
+    assert np.array_equal(q, q0) and np.array_equal(r, r0)
+
+
+@pytest.mark.parametrize("m,n,kappa,seed,depth", [
+    (2000, 37, 1e6, 3, 1), (2000, 37, 1e6, 3, 3), (5000, 64, 1e4, 13, 2), (700, 100, 1e6, 14, 4)])
+def test_cqr2_partial_matches_householder(m, n, kappa, seed, depth):
+    a = gdv_matrix(m, n, kappa, seed)
+    q, r = oracle.cqr2_partial(a, depth)
+    qh, rh = oracle.householder_qr_posdiag(a)
+    assert oracle.orthogonality(q) <= 1e-12
+    assert oracle.residual(a, q, r) <= 1e-13
+    assert oracle.rel_fro(r, rh) <= 1e-9
+    assert np.array_equal(r, np.triu(r)) and np.all(np.diag(r) > 0)
+
+
+def test_cqr2_partial_power_of_two_scaling_is_exact():
+    a = gdv_matrix(400, 24, 1e3, 15)
+    q, r = oracle.cqr2_partial(a, 2)
+    q2, r2 = oracle.cqr2_partial(a * 2.0 ** 10, 2)
+    assert np.array_equal(q2, q) and np.array_equal(r2, r * 2.0 ** 10)
+
+
+def test_cqr2_partial_breakdown_columns():
+    a = gdv_matrix(300, 20, 10.0, 16)
+    a[:, 13] = 0.0
+    with pytest.raises(oracle.NotSPD) as e:
+        oracle.cqr2_partial(a, 2)
+    assert e.value.j == 14
+
+
+@pytest.mark.parametrize("kind", ["sign", "no_transpose", "skip_update"])
+def test_pins_catch_planted_block_substitution_mistakes(kind, monkeypatch):
+    def mut(b, l, y, blocks):
+        b = np.asarray(b, dtype=np.float64)
+        x = np.zeros_like(b)
+        for c0, c1 in blocks:
+            if kind == "sign":
+                t = b[:, c0:c1] + x[:, :c0] @ l[c0:c1, :c0].T
+            elif kind == "no_transpose":
+                t = b[:, c0:c1] - x[:, :c0] @ l[:c0, c0:c1]
+            else:
+                t = b[:, c0:c1]
+            x[:, c0:c1] = t @ y[c0:c1, c0:c1].T
+        return x
+    d = _gold("cholinv_exact_n13.json")
+    monkeypatch.setattr(cqr2_ref, "solve_right_lt", mut)
+    try:
+        l, y, blocks = cqr2_ref.cholinv_partial(np.array(d["W"]), 2)
+        exact_ok = np.array_equal(l, np.array(d["L"]))
+    except oracle.NotSPD:
+        exact_ok = False
+    assert not exact_ok
+    a = gdv_matrix(300, 16, 1e3, 17)
+    try:
+        q, r = cqr2_ref.cqr2_partial(a, 2)
+        qh, rh = oracle.householder_qr_posdiag(a)
+        good = oracle.rel_fro(r, rh) <= 1e-9 and oracle.orthogonality(q) <= 1e-12
+    except oracle.NotSPD:
+        good = False
+    assert not good
