@@ -238,6 +238,8 @@ def main():
     ap.add_argument("--kappa", type=float, default=None, help="condition number (mixed_262144x256 sweep)")
     ap.add_argument("--mixed", action="store_true", help="CQR2_MIXED_P1_FP32 (pass-1 Q1 in FP32)")
     ap.add_argument("--shifted", action="store_true", help="CQR2_SHIFTED_CQR3 (shifted CholeskyQR3)")
+    ap.add_argument("--inverse-depth", type=int, default=0,
+                    help="CQR2_INVERSE_DEPTH(d): partial inverse, Q by block substitution (n > 128)")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
@@ -270,7 +272,9 @@ def main():
     wl = WORKLOADS[args.workload]
     m, n = wl.m, wl.n
     flags = cq.CQR2_MIXED_P1_FP32 if args.mixed else (cq.CQR2_SHIFTED_CQR3 if args.shifted else cq.CQR2_FP64)
-    default_run = args.workload == "tall_1Mx128" and not args.mixed and not args.shifted
+    flags |= cq.CQR2_INVERSE_DEPTH(args.inverse_depth)
+    default_run = (args.workload == "tall_1Mx128" and not args.mixed and not args.shifted
+                   and args.inverse_depth == 0)
     log(f"generating {wl.description} (seed {wl.seed}) on the host ...")
     t0 = time.perf_counter()
     a_host = workload_matrix(args.workload, args.kappa)
@@ -348,7 +352,8 @@ def main():
 
     out = {
         "metric": METRIC if default_run else
-        f"CQR2 GFLOP/s ({args.workload}{' mixed' if args.mixed else ''}{' shifted CQR3' if args.shifted else ''})",
+        f"CQR2 GFLOP/s ({args.workload}{' mixed' if args.mixed else ''}{' shifted CQR3' if args.shifted else ''}"
+        f"{f' inverse depth {args.inverse_depth}' if args.inverse_depth else ''})",
         "value": round(value, 2),
         "unit": "GFLOP/s",
         "n_gpus": 1,
@@ -363,7 +368,9 @@ def main():
         "config": {"workload": args.workload, "m": m, "n": n, "lda": m,
                    "kappa": args.kappa if args.kappa is not None else wl.kappa, "seed": wl.seed,
                    "flags": "CQR2_MIXED_P1_FP32" if args.mixed else
-                   ("CQR2_SHIFTED_CQR3" if args.shifted else "CQR2_FP64"), "matrix": wl.description},
+                   ("CQR2_SHIFTED_CQR3" if args.shifted else "CQR2_FP64")
+                   + (f" | CQR2_INVERSE_DEPTH({args.inverse_depth})" if args.inverse_depth else ""),
+                   "matrix": wl.description},
         "hbm_roofline_pct_6mn": round(100.0 * hbm_bytes_6mn / t_step / 1e9 / HBM_PEAK_GBS, 2),
         "paper_convention_gflops": round(flops_householder(m, n) / t_step / 1e9, 2),
         "class_ms": {k: round(v[0] / v[1], 5) for k, v in kt.items() if v[1]},

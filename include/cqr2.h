@@ -64,6 +64,19 @@ extern "C" {
  * Accepted by cqr2_factor_ex / cqr2_workspace_size. */
 #define CQR2_SHIFTED_CQR3 2u
 
+/* Partial inverse (the paper's alternative for 3D-CQR2, tuned in its
+ * experiments as InverseDepth): OR'ed onto CQR2_FP64, CQR2_INVERSE_DEPTH(d),
+ * 1 <= d <= 8, stops forming the triangular inverse in the top d levels of the
+ * CholInv recursion (Algorithm 2's Y21 is skipped there), so R^{-1} is kept
+ * only as inverted diagonal blocks; L21 inside the recursion and Q = A R^{-1}
+ * are then formed by block substitution, one GEMM pair per block.  The
+ * recursion splits at multiples of 128 and stops at n <= 128, so the blocks are
+ * at least 128 wide and the flag changes nothing for n <= 128.  FP64 only
+ * (not with CQR2_MIXED_P1_FP32 or CQR2_SHIFTED_CQR3).  Accepted by
+ * cqr2_factor_ex / cqr2_workspace_size. */
+#define CQR2_INVERSE_DEPTH(d) (((uint32_t)(d)) << 8)
+#define CQR2_MAX_INVERSE_DEPTH 8
+
 /* Largest n accepted (every n x n workspace block is n*n*8 bytes).  Up to
  * n = 128 the tall-skinny kernels run (split-K Gram, one-workgroup CholInv,
  * streaming Q = A R^{-1}); above, the Gram, Q formation and R2 R1 are tiled

@@ -22,6 +22,12 @@ CQR2_ERR_TOO_LARGE = -102
 CQR2_FP64 = 0
 CQR2_MIXED_P1_FP32 = 1
 CQR2_SHIFTED_CQR3 = 2
+CQR2_MAX_INVERSE_DEPTH = 8
+
+
+def CQR2_INVERSE_DEPTH(d: int) -> int:
+    """Flag bits of the partial inverse with depth d (OR onto CQR2_FP64)."""
+    return int(d) << 8
 NUM_TIMERS = 6
 TIMER_NAMES = ("gram", "gram_reduce", "cholinv", "apply_rinv_pass1", "apply_rinv_pass2", "upper_product")
 

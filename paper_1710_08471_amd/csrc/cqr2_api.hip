@@ -71,17 +71,26 @@ SmallLayout make_small_layout(int64_t m, int64_t n) {
 
 // FP64 factorizations with n <= 128 run the tall-skinny kernels; everything
 // else (n > 128, and the mixed-precision form at any n) runs the tiled path.
+// flags: the form in the low byte, the inverse depth above it
+uint32_t flag_form(uint32_t flags) { return flags & 0xffu; }
+int flag_depth(uint32_t flags) { return (int)(flags >> 8); }
+
 bool use_small(int64_t n, uint32_t flags) {
-  return n <= kSmallN && (flags == CQR2_FP64 || flags == CQR2_SHIFTED_CQR3);
+  // (the recursion behind the inverse depth has no level at n <= 128)
+  return n <= kSmallN && (flag_form(flags) == CQR2_FP64 || flag_form(flags) == CQR2_SHIFTED_CQR3);
 }
 
 bool valid_flags(uint32_t flags) {
-  return flags == CQR2_FP64 || flags == CQR2_MIXED_P1_FP32 || flags == CQR2_SHIFTED_CQR3;
+  const uint32_t f = flag_form(flags);
+  const int d = flag_depth(flags);
+  if (f != CQR2_FP64 && f != CQR2_MIXED_P1_FP32 && f != CQR2_SHIFTED_CQR3) return false;
+  return d >= 0 && d <= CQR2_MAX_INVERSE_DEPTH && (d == 0 || f == CQR2_FP64);
 }
 
 size_t factor_workspace(int64_t m, int64_t n, uint32_t flags) {
   return use_small(n, flags) ? make_small_layout(m, n).total
-                             : cqr2::plan_general(m, n, flags == CQR2_MIXED_P1_FP32).total;
+                             : cqr2::plan_general(m, n, flag_form(flags) == CQR2_MIXED_P1_FP32,
+                                                  flag_depth(flags)).total;
 }
 
 // ---- timing instrumentation -------------------------------------------------
@@ -220,13 +229,14 @@ int run_small(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, int
 
 int run_factor(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, int64_t ldq, double* R, int64_t ldr,
                char* ws, int32_t* d_info, uint32_t flags, hipStream_t s) {
-  const bool shifted = flags == CQR2_SHIFTED_CQR3;
+  const bool shifted = flag_form(flags) == CQR2_SHIFTED_CQR3;
   if (use_small(n, flags))
     return run_small(A, m, n, lda, Q, ldq, R, ldr, ws, make_small_layout(m, n), d_info, s, device_cus(), shifted);
-  const bool mixed = flags == CQR2_MIXED_P1_FP32;
-  const cqr2::GeneralPlan p = cqr2::plan_general(m, n, mixed);
-  return check_hip(
-      cqr2::factor_general(A, m, n, lda, Q, ldq, R, ldr, ws, p, mixed, d_info, s, timer_hook(), shifted));
+  const bool mixed = flag_form(flags) == CQR2_MIXED_P1_FP32;
+  const int depth = flag_depth(flags);
+  const cqr2::GeneralPlan p = cqr2::plan_general(m, n, mixed, depth);
+  return check_hip(cqr2::factor_general(A, m, n, lda, Q, ldq, R, ldr, ws, p, mixed, d_info, s, timer_hook(),
+                                        shifted, depth));
 }
 
 }  // namespace

@@ -19,6 +19,22 @@ int64_t cholinv_split(int64_t n) {
   return h < kBaseN ? kBaseN : h;
 }
 
+int inverse_blocks(int64_t n, int depth, Block* out, int cap) {
+  if (cap < 1) return 0;
+  if (depth <= 0 || n <= kBaseN) {
+    out[0] = {0, n};
+    return 1;
+  }
+  const int64_t h = cholinv_split(n);
+  const int a = inverse_blocks(h, depth - 1, out, cap);
+  const int b = inverse_blocks(n - h, depth - 1, out + a, cap - a);
+  for (int i = a; i < a + b; ++i) {
+    out[i].c0 += h;
+    out[i].c1 += h;
+  }
+  return a + b;
+}
+
 // Reduction splits used by every GEMM of the recursion, fixed by the shape only.
 static int rec_splits(int64_t M, int64_t N, int64_t K) { return gemm_pick_splits(M, N, K, kPlanCUs); }
 
@@ -63,7 +79,7 @@ static hipError_t zero_block(double* X, int64_t ldx, int64_t rows, int64_t cols,
 // Schur complements.  R, Rinv: n x n upper (ldr, ldri), strictly lower parts 0.
 // work: >= cholinv_rec_workspace(n) bytes.
 hipError_t cholinv_recursive(double* W, int64_t ldw, int64_t n, double* R, int64_t ldr, double* Rinv, int64_t ldri,
-                             char* work, int32_t* info, int info_offset, hipStream_t s) {
+                             char* work, int32_t* info, int info_offset, hipStream_t s, int depth) {
   if (n <= kBaseN) return launch_cholinv(W, ldw, (int)n, R, ldr, Rinv, ldri, nullptr, 0, info, info_offset, s);
   const int64_t h = cholinv_split(n), n2 = n - h;
   double* W22 = W + h + h * ldw;
@@ -73,21 +89,45 @@ hipError_t cholinv_recursive(double* W, int64_t ldw, int64_t n, double* R, int64
   double* Ri22 = Rinv + h + h * ldri;
   double* T = (double*)work;
   double* gws = (double*)(work + (size_t)h * n2 * sizeof(double));
+  const int sub = depth > 0 ? depth - 1 : 0;
   // L11, Y11 = CholInv(A11)
-  CQR2_HIP(cholinv_recursive(W, ldw, h, R, ldr, Rinv, ldri, work, info, info_offset, s));
-  // L21 = A21 Y11ᵀ, kept as R12 = L21ᵀ = Y11 A21ᵀ = Rinv11ᵀ A21ᵀ
-  CQR2_HIP(launch_gemm(1, 1, h, n2, h, 1.0, Rinv, ldri, W + h, ldw, 0.0, R12, ldr, GEMM_A_LOWER,
-                       rec_splits(h, n2, h), gws, info, s));
+  CQR2_HIP(cholinv_recursive(W, ldw, h, R, ldr, Rinv, ldri, work, info, info_offset, s, sub));
+  if (depth == 0) {
+    // L21 = A21 Y11ᵀ, kept as R12 = L21ᵀ = Y11 A21ᵀ = Rinv11ᵀ A21ᵀ
+    CQR2_HIP(launch_gemm(1, 1, h, n2, h, 1.0, Rinv, ldri, W + h, ldw, 0.0, R12, ldr, GEMM_A_LOWER,
+                         rec_splits(h, n2, h), gws, info, s));
+  } else {
+    // L21 = A21 L11^{-T} by block substitution over the inverted diagonal
+    // blocks of Y11: per block b, T = A21(:, b) - L21(:, <b) L11(b, <b)ᵀ
+    // (= A21(:, b) - R12(<b, :)ᵀ R11(<b, b)), then R12(b, :) = (T Y_bbᵀ)ᵀ =
+    // Rinv_bbᵀ Tᵀ.  T (n2 x width) lives in the scratch block.
+    Block blk[256];
+    const int nb = inverse_blocks(h, sub, blk, 256);
+    for (int i = 0; i < nb; ++i) {
+      const int64_t c0 = blk[i].c0, b = blk[i].c1 - blk[i].c0;
+      CQR2_HIP(hipMemcpy2DAsync(T, n2 * sizeof(double), W + h + c0 * ldw, ldw * sizeof(double), n2 * sizeof(double),
+                                b, hipMemcpyDeviceToDevice, s));
+      if (c0 > 0)
+        CQR2_HIP(launch_gemm(1, 0, n2, b, c0, -1.0, R12, ldr, R + c0 * ldr, ldr, 1.0, T, n2, 0, 1, nullptr, info,
+                             s));
+      CQR2_HIP(launch_gemm(1, 1, b, n2, b, 1.0, Rinv + c0 + c0 * ldri, ldri, T, n2, 0.0, R12 + c0, ldr,
+                           GEMM_A_LOWER, 1, nullptr, info, s));
+    }
+  }
   // A22 - L21 L21ᵀ = A22 - R12ᵀ R12 (lower triangle)
   CQR2_HIP(launch_gemm(1, 0, n2, n2, h, -1.0, R12, ldr, R12, ldr, 1.0, W22, ldw, GEMM_C_LOWER,
                        rec_splits(n2, n2, h), gws, info, s));
   // L22, Y22 = CholInv(A22 - L21 L21ᵀ)
-  CQR2_HIP(cholinv_recursive(W22, ldw, n2, R22, ldr, Ri22, ldri, work, info, info_offset + (int)h, s));
-  // Y21 = -Y22 (L21 Y11): in the transposed factors, Rinv12 = -(Rinv11 R12) Rinv22
-  CQR2_HIP(launch_gemm(0, 0, h, n2, h, 1.0, Rinv, ldri, R12, ldr, 0.0, T, h, GEMM_A_UPPER, rec_splits(h, n2, h), gws,
-                       info, s));
-  CQR2_HIP(launch_gemm(0, 0, h, n2, n2, -1.0, T, h, Ri22, ldri, 0.0, Ri12, ldri, GEMM_B_UPPER,
-                       rec_splits(h, n2, n2), gws, info, s));
+  CQR2_HIP(cholinv_recursive(W22, ldw, n2, R22, ldr, Ri22, ldri, work, info, info_offset + (int)h, s, sub));
+  if (depth == 0) {
+    // Y21 = -Y22 (L21 Y11): in the transposed factors, Rinv12 = -(Rinv11 R12) Rinv22
+    CQR2_HIP(launch_gemm(0, 0, h, n2, h, 1.0, Rinv, ldri, R12, ldr, 0.0, T, h, GEMM_A_UPPER, rec_splits(h, n2, h),
+                         gws, info, s));
+    CQR2_HIP(launch_gemm(0, 0, h, n2, n2, -1.0, T, h, Ri22, ldri, 0.0, Ri12, ldri, GEMM_B_UPPER,
+                         rec_splits(h, n2, n2), gws, info, s));
+  } else {
+    CQR2_HIP(zero_block(Ri12, ldri, h, n2, s));  // Y21 is not formed at this level
+  }
   // strictly lower blocks of the triangular factors
   CQR2_HIP(zero_block(R + h, ldr, n2, h, s));
   CQR2_HIP(zero_block(Rinv + h, ldri, n2, h, s));
@@ -166,7 +206,7 @@ hipError_t launch_finalize_r(const double* P, int64_t ldp, double* R, int64_t ld
 }
 
 // ---- CholeskyQR2 for n > 128 ------------------------------------------------
-GeneralPlan plan_general(int64_t m, int64_t n, bool mixed) {
+GeneralPlan plan_general(int64_t m, int64_t n, bool mixed, int depth) {
   GeneralPlan p{};
   p.gram_splits = gemm_pick_splits(n, n, m, kPlanCUs);
   p.apply_splits = 1;
@@ -191,13 +231,43 @@ GeneralPlan plan_general(int64_t m, int64_t n, bool mixed) {
   const size_t rws = cholinv_rec_workspace(n);
   p.off_scratch = take(gws > rws ? gws : rws);
   p.off_q1 = take((size_t)m * n * (mixed ? sizeof(float) : sizeof(double)));
+  if (depth > 0) {
+    Block blk[256];
+    const int nb = inverse_blocks(n, depth, blk, 256);
+    int64_t wmax = 0;
+    for (int i = 0; i < nb; ++i) wmax = blk[i].c1 - blk[i].c0 > wmax ? blk[i].c1 - blk[i].c0 : wmax;
+    p.off_t = take((size_t)m * wmax * sizeof(double));
+  }
   p.total = off;
   return p;
 }
 
+// Y = X R^{-1} with R^{-1} kept as inverted diagonal blocks (the partial
+// inverse): for each block b in order, Y(:, b) = (X(:, b) - Y(:, <b) R(<b, b))
+// R^{-1}_bb -- the copy, one GEMM and one triangular multiply per block.
+static hipError_t block_solve(const double* X, int64_t ldx, int64_t m, int64_t n, double* Y, int64_t ldy,
+                              const double* R, const double* Rinv, int depth, double* Uimg, double* T,
+                              const int32_t* info, hipStream_t s) {
+  Block blk[256];
+  const int nb = inverse_blocks(n, depth, blk, 256);
+  for (int i = 0; i < nb; ++i) {
+    const int64_t c0 = blk[i].c0, b = blk[i].c1 - blk[i].c0;
+    CQR2_HIP(launch_upper_image(Rinv + c0 + c0 * n, n, (int)b, Uimg, s));
+    if (c0 == 0) {
+      CQR2_HIP(launch_tall_gemm(0, X, m, (int)b, ldx, Uimg, Y, ldy, info, s));
+      continue;
+    }
+    CQR2_HIP(hipMemcpy2DAsync(T, m * sizeof(double), X + c0 * ldx, ldx * sizeof(double), m * sizeof(double), b,
+                              hipMemcpyDeviceToDevice, s));
+    CQR2_HIP(launch_gemm(0, 0, m, b, c0, -1.0, Y, ldy, R + c0 * n, n, 1.0, T, m, 0, 1, nullptr, info, s));
+    CQR2_HIP(launch_tall_gemm(0, T, m, (int)b, m, Uimg, Y + c0 * ldy, ldy, info, s));
+  }
+  return hipSuccess;
+}
+
 hipError_t factor_general(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, int64_t ldq, double* R,
                           int64_t ldr, char* ws, const GeneralPlan& p, bool mixed, int32_t* d_info, hipStream_t s,
-                          const TimerHook& th, bool shifted) {
+                          const TimerHook& th, bool shifted, int depth) {
   int32_t* info = (int32_t*)(ws + p.off_info);
   double* W = (double*)(ws + p.off_w);
   double* R1 = (double*)(ws + p.off_r1);
@@ -223,15 +293,19 @@ hipError_t factor_general(const double* A, int64_t m, int64_t n, int64_t lda, do
   th.end(0, s);
   if (shifted) CQR2_HIP(launch_shift_diag(W, n, n, m, info, s));
   th.begin(2, s);
-  CQR2_HIP(cholinv_recursive(W, n, n, R1, n, Ri1, n, scratch, info, 0, s));
+  CQR2_HIP(cholinv_recursive(W, n, n, R1, n, Ri1, n, scratch, info, 0, s, depth));
   th.end(2, s);
   th.begin(3, s);
-  // the tall kernel reads R^{-1} as its zero-padded row-major image
-  CQR2_HIP(launch_upper_image(Ri1, n, (int)n, Uimg, s));
-  if (mixed)
-    CQR2_HIP(launch_tall_gemm_f32(A, m, (int)n, lda, Uimg, (float*)Q1, m, info, s));
-  else
-    CQR2_HIP(launch_tall_gemm(0, A, m, (int)n, lda, Uimg, (double*)Q1, m, info, s));
+  if (depth > 0) {
+    CQR2_HIP(block_solve(A, lda, m, n, (double*)Q1, m, R1, Ri1, depth, Uimg, (double*)(ws + p.off_t), info, s));
+  } else {
+    // the tall kernel reads R^{-1} as its zero-padded row-major image
+    CQR2_HIP(launch_upper_image(Ri1, n, (int)n, Uimg, s));
+    if (mixed)
+      CQR2_HIP(launch_tall_gemm_f32(A, m, (int)n, lda, Uimg, (float*)Q1, m, info, s));
+    else
+      CQR2_HIP(launch_tall_gemm(0, A, m, (int)n, lda, Uimg, (double*)Q1, m, info, s));
+  }
   th.end(3, s);
   // pass 2: CQR(Q1) -> Q, R2, on the stored Q1 values (FP32 ones widen exactly)
   th.begin(0, s);
@@ -244,11 +318,15 @@ hipError_t factor_general(const double* A, int64_t m, int64_t n, int64_t lda, do
                               (double*)scratch, info, s));
   th.end(0, s);
   th.begin(2, s);
-  CQR2_HIP(cholinv_recursive(W, n, n, R2, n, Ri2, n, scratch, info, (int)n, s));
+  CQR2_HIP(cholinv_recursive(W, n, n, R2, n, Ri2, n, scratch, info, (int)n, s, depth));
   th.end(2, s);
   th.begin(4, s);
-  CQR2_HIP(launch_upper_image(Ri2, n, (int)n, Uimg, s));
-  CQR2_HIP(launch_tall_gemm(q1f, Q1, m, (int)n, m, Uimg, Q, ldq, info, s));
+  if (depth > 0) {
+    CQR2_HIP(block_solve((const double*)Q1, m, m, n, Q, ldq, R2, Ri2, depth, Uimg, (double*)(ws + p.off_t), info, s));
+  } else {
+    CQR2_HIP(launch_upper_image(Ri2, n, (int)n, Uimg, s));
+    CQR2_HIP(launch_tall_gemm(q1f, Q1, m, (int)n, m, Uimg, Q, ldq, info, s));
+  }
   th.end(4, s);
   constexpr int kUp = GEMM_A_UPPER | GEMM_B_UPPER | GEMM_C_UPPER;
   if (!shifted) {

@@ -132,8 +132,11 @@ hipError_t launch_syrk(const SyrkPlan& p, const double* A, int64_t m, int n, int
 int64_t cholinv_split(int64_t n);
 size_t cholinv_rec_workspace(int64_t n);
 // W (n x n, ldw, lower read, trailing blocks overwritten) -> R, Rinv upper.
+// depth > 0: the top `depth` levels skip the off-diagonal inverse block, so
+// Rinv holds only the inverses of the inverse_blocks(n, depth) diagonal
+// blocks (zero elsewhere), and R12 is formed by block substitution.
 hipError_t cholinv_recursive(double* W, int64_t ldw, int64_t n, double* R, int64_t ldr, double* Rinv, int64_t ldri,
-                             char* work, int32_t* info, int info_offset, hipStream_t s);
+                             char* work, int32_t* info, int info_offset, hipStream_t s, int depth = 0);
 // R = triu(P), or NaN after a breakdown; copies the info word to user_info.
 hipError_t launch_finalize_r(const double* P, int64_t ldp, double* R, int64_t ldr, int64_t n, const int32_t* info,
                              int32_t* user_info, hipStream_t s);
@@ -144,15 +147,24 @@ hipError_t launch_mirror_lower(double* W, int64_t ldw, int64_t n, hipStream_t s)
 struct GeneralPlan {
   int gram_splits = 1, apply_splits = 1;
   size_t off_info = 0, off_w = 0, off_r1 = 0, off_ri1 = 0, off_r2 = 0, off_ri2 = 0, off_p = 0, off_uimg = 0,
-         off_scratch = 0, off_q1 = 0;
+         off_scratch = 0, off_q1 = 0, off_t = 0;
   size_t total = 0;
 };
 // mixed: pass 1's Q1 = A R1^-1 is formed with FP32 products and sums and kept
 // as an FP32 m x n block in the workspace (everything else stays FP64).
-GeneralPlan plan_general(int64_t m, int64_t n, bool mixed);
+// depth > 0: the partial inverse (inverse_blocks); the plan then holds an
+// m x (widest block) FP64 buffer at off_t for the block substitution.
+GeneralPlan plan_general(int64_t m, int64_t n, bool mixed, int depth = 0);
 hipError_t factor_general(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, int64_t ldq, double* R,
                           int64_t ldr, char* ws, const GeneralPlan& p, bool mixed, int32_t* d_info, hipStream_t s,
-                          const TimerHook& th, bool shifted = false);
+                          const TimerHook& th, bool shifted = false, int depth = 0);
+// Diagonal blocks [start, stop) whose inverses the CholInv recursion forms
+// when the top `depth` levels skip the off-diagonal inverse block (the
+// recursion's own split points; depth 0 or n <= 128: one block).
+struct Block {
+  int64_t c0, c1;
+};
+int inverse_blocks(int64_t n, int depth, Block* out, int cap);
 // Adds s = 11 (m n + n (n + 1)) 2^-53 trace(W) to the diagonal of W (shifted CholeskyQR).
 hipError_t launch_shift_diag(double* W, int64_t ldw, int64_t n, int64_t m, const int32_t* info, hipStream_t s);
 

@@ -221,3 +221,22 @@ def test_lstsq_argument_errors():
     assert call(W=ctypes.c_void_p(0x5000008)) == -14
     assert call(wb=ws - 1) == -15
     assert call(info=ctypes.c_void_p(0x6000002)) == -16
+
+
+def test_inverse_depth_flags():
+    lib = cq.load()
+    d = cq.CQR2_INVERSE_DEPTH
+    ws0 = lib.cqr2_workspace_size(5000, 600, 0)
+    # the block substitution's m x (widest block) buffer is added on the tiled path
+    assert lib.cqr2_workspace_size(5000, 600, d(1)) > ws0
+    assert lib.cqr2_workspace_size(5000, 600, d(cq.CQR2_MAX_INVERSE_DEPTH)) > ws0
+    # no recursion level at n <= 128: the flag changes nothing there
+    assert lib.cqr2_workspace_size(5000, 100, d(2)) == lib.cqr2_workspace_size(5000, 100, 0)
+    assert lib.cqr2_workspace_size(5000, 600, d(cq.CQR2_MAX_INVERSE_DEPTH + 1)) == 0
+    assert lib.cqr2_workspace_size(5000, 600, d(1) | cq.CQR2_MIXED_P1_FP32) == 0
+    assert lib.cqr2_workspace_size(5000, 600, d(1) | cq.CQR2_SHIFTED_CQR3) == 0
+    f = lib.cqr2_factor_ex
+    W = ctypes.c_void_p(0x40000000)
+    for flags in (d(9), d(1) | 1, d(2) | 2, 3 | d(1)):
+        assert f(FAKE, 100, 10, 100, FAKE2, 100, ctypes.c_void_p(0x30000000), 10, W, 1 << 30, NULL, flags,
+                 NULL) == -12
