@@ -21,8 +21,8 @@ namespace cqr2 {
 // stages (asynchronous global -> LDS copies, double-buffered, 512 contiguous
 // bytes per column), so only A fragments are read from LDS and the bytes in
 // flight cost no registers.  Stores of a stage are issued at the start of the
-// next iteration and target rows no later load touches, so Q == A (in place)
-// is safe.
+// next iteration and target rows no later load touches (the stages run in one
+// direction), so Q == A (in place) is safe.
 // ============================================================================
 constexpr int kApplyRows = 64;  // rows per stage (4 tiles of 16)
 constexpr int kApplyTiles = kApplyRows / 16;
@@ -137,7 +137,7 @@ struct ApplyWave {
 template <int NT, int W>
 __device__ __forceinline__ void apply_wave_run(const double* A, int64_t m, int n, int64_t lda,
                                                const double* __restrict__ U, int64_t urs, int64_t ucs, double* Q,
-                                               int64_t ldq, int64_t s_begin, int64_t s_end, int64_t s_stride,
+                                               int64_t ldq, int64_t s_begin, int64_t s_end, bool descending,
                                                double* sa, bool direct_ok) {
   using AW = ApplyWave<NT, W>;
   using L = typename AW::L;
@@ -178,8 +178,10 @@ __device__ __forceinline__ void apply_wave_run(const double* A, int64_t m, int n
   for (int e = tid; e < 2 * kBuf; e += kThreads)
     if ((e % kBuf) / kApplyRows >= n) sa[e] = 0.0;
 
-  int64_t st = s_begin;
-  if (st < s_end) fill(st, sa);
+  // stages s_begin .. s_end - 1, in ascending or descending order
+  const int64_t count = s_end - s_begin;
+  auto stage_at = [&](int64_t i) { return descending ? s_end - 1 - i : s_begin + i; };
+  if (count > 0) fill(stage_at(0), sa);
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
 
@@ -201,10 +203,10 @@ __device__ __forceinline__ void apply_wave_run(const double* A, int64_t m, int n
   };
   int cur = 0;
   int64_t prev = -1;
-  for (; st < s_end; st += s_stride) {
+  for (int64_t i = 0; i < count; ++i) {
+    const int64_t st = stage_at(i);
     if (prev >= 0) store(prev);
-    const int64_t nxt = st + s_stride;
-    if (nxt < s_end) fill(nxt, sa + (cur ^ 1) * kBuf);
+    if (i + 1 < count) fill(stage_at(i + 1), sa + (cur ^ 1) * kBuf);
 #pragma unroll
     for (int rt = 0; rt < kApplyTiles; ++rt)
 #pragma unroll
@@ -218,17 +220,17 @@ __device__ __forceinline__ void apply_wave_run(const double* A, int64_t m, int n
   if (prev >= 0) store(prev);
 }
 
-// All waves of a workgroup: Q = A U over the 64-row stages s_begin,
-// s_begin + s_stride, ... below s_end.
+// All waves of a workgroup: Q = A U over the 64-row stages s_begin ..
+// s_end - 1, taken in descending order if `descending`.
 template <int NT>
 __device__ __forceinline__ void apply_block(const double* A, int64_t m, int n, int64_t lda,
                                             const double* __restrict__ U, int64_t urs, int64_t ucs, double* Q,
-                                            int64_t ldq, int64_t s_begin, int64_t s_end, int64_t s_stride,
+                                            int64_t ldq, int64_t s_begin, int64_t s_end, bool descending,
                                             double* sa) {
   const bool direct_ok = (((uintptr_t)A & 15u) == 0) && ((lda & 1) == 0);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   constexpr int W = ApplyLayout<NT / 4>::W;
-#define CQR2_AW(WV) apply_wave_run<NT, WV>(A, m, n, lda, U, urs, ucs, Q, ldq, s_begin, s_end, s_stride, sa, direct_ok)
+#define CQR2_AW(WV) apply_wave_run<NT, WV>(A, m, n, lda, U, urs, ucs, Q, ldq, s_begin, s_end, descending, sa, direct_ok)
   switch (wave) {
     case 0: CQR2_AW(0); break;
     case 1: if constexpr (W > 1) CQR2_AW(1); break;

@@ -16,14 +16,16 @@ __global__ __launch_bounds__(64 * ApplyLayout<NT / 4>::W, 1) void k_apply_rinv(
     double* Q, int64_t ldq, const int32_t* __restrict__ info, int nwg) {
   // nwg == gridDim.x.  Each workgroup takes a contiguous range of stages
   // (measured slightly faster than dealing them round-robin: the workgroups'
-  // concurrent accesses then spread over the whole of A and Q).
+  // concurrent accesses then spread over the whole of A and Q), walked from
+  // its end: the Gram before this kernel reads the same ranges upwards, so the
+  // rows it read last come first.
   __shared__ double sa[2 * NT * kApplyRows];
   if (info != nullptr && *info != 0) return;
   const int64_t stages = (m + kApplyRows - 1) / kApplyRows;
   const int64_t per = (stages + nwg - 1) / nwg;
   const int64_t s0 = (int64_t)blockIdx.x * per;
   const int64_t s1 = s0 + per < stages ? s0 + per : stages;
-  apply_block<NT>(A, m, n, lda, U, urs, ucs, Q, ldq, s0, s1, 1, sa);
+  apply_block<NT>(A, m, n, lda, U, urs, ucs, Q, ldq, s0, s1, true, sa);
 }
 
 hipError_t launch_apply_rinv(const double* A, int64_t m, int n, int64_t lda, const double* U, int64_t urs,

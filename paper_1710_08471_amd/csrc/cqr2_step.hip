@@ -106,7 +106,7 @@ __device__ __forceinline__ void step_run(const StepTask& t, int sub, double* lds
     }
     case 2:
       if (*info != 0) return;
-      apply_block<NT>(t.A, m, n, t.lda, U1, NP, 1, t.Q, t.ldq, s0, s1, 1, lds);
+      apply_block<NT>(t.A, m, n, t.lda, U1, NP, 1, t.Q, t.ldq, s0, s1, false, lds);
       break;
     case 5: {
       const int32_t st = *info;
@@ -116,7 +116,7 @@ __device__ __forceinline__ void step_run(const StepTask& t, int sub, double* lds
         return;
       }
       if (st != 0) return;
-      apply_block<NT>(t.Q, m, n, t.ldq, U2, NP, 1, t.Q, t.ldq, s0, s1, 1, lds);
+      apply_block<NT>(t.Q, m, n, t.ldq, U2, NP, 1, t.Q, t.ldq, s0, s1, false, lds);
       break;
     }
     default: break;
