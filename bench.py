@@ -47,7 +47,7 @@ KERNEL_CLASSES = {
     "k_gram_partials": ("gram",),
     "k_gram_reduce": ("gram_reduce",),
     "k_cholinv": ("cholinv",),
-    "k_gemm+k_finalize_r": ("upper_product",),
+    "k_upper_product_final": ("upper_product",),
 }
 
 

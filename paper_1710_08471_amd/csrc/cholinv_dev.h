@@ -61,8 +61,17 @@ __device__ __forceinline__ double cholinv_src(const CholInvSrc& s, int p, int q)
   const int I = p >> 2, J = q >> 2;
   const int64_t e = (int64_t)(I * (I + 1) / 2 + J) * 16 + (p & 3) * 4 + (q & 3);
   const int64_t stride = (int64_t)s.nblk * 16;
+  // split order; the loads go out eight at a time
   double v = 0.0;
-  for (int k = 0; k < s.splits; ++k) v += s.part[e + k * stride];
+  int k = 0;
+  for (; k + 8 <= s.splits; k += 8) {
+    double x[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) x[j] = s.part[e + (k + j) * stride];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v += x[j];
+  }
+  for (; k < s.splits; ++k) v += s.part[e + k * stride];
   return v;
 }
 

@@ -193,24 +193,28 @@ int run_small(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, int
   double* R1 = (double*)(ws + L.off_r1);
   double* R2 = (double*)(ws + L.off_r2);
   const int ni = (int)n;
-  CQR2_TRY(cqr2::launch_set_info(info, 0, s));
-  // ---- pass 1: CQR(A) ----
-  th.begin(0, s); CQR2_TRY(cqr2::launch_gram_partials(L.gram, A, m, ni, lda, part, info, s)); th.end(0, s);
-  th.begin(1, s); CQR2_TRY(cqr2::launch_gram_reduce(L.gram, part, ni, W, n, info, s)); th.end(1, s);
-  if (shifted) CQR2_TRY(cqr2::launch_shift_diag(W, n, n, m, info, s));
-  th.begin(2, s); CQR2_TRY(cqr2::launch_cholinv(W, n, ni, R1, n, nullptr, 0, U1, L.np, info, 0, s)); th.end(2, s);
+  auto cholinv = [&](double* Rk, double* Uk, int info_offset) -> int {
+    th.begin(1, s); CQR2_TRY(cqr2::launch_gram_reduce(L.gram, part, ni, W, n, info, s)); th.end(1, s);
+    if (shifted && info_offset == 0) CQR2_TRY(cqr2::launch_shift_diag(W, n, n, m, info, s));
+    th.begin(2, s); CQR2_TRY(cqr2::launch_cholinv(W, n, ni, Rk, n, nullptr, 0, Uk, L.np, info, info_offset, s));
+    th.end(2, s);
+    return 0;
+  };
+  // ---- pass 1: CQR(A); the first Gram clears the info word ----
+  th.begin(0, s);
+  CQR2_TRY(cqr2::launch_gram_partials(L.gram, A, m, ni, lda, part, nullptr, s, info));
+  th.end(0, s);
+  if (const int rc = cholinv(R1, U1, 0)) return rc;
   th.begin(3, s); CQR2_TRY(cqr2::launch_apply_rinv(A, m, ni, lda, U1, L.np, 1, Q, ldq, info, cus, s)); th.end(3, s);
   // ---- pass 2: CQR(Q1), in place ----
   th.begin(0, s); CQR2_TRY(cqr2::launch_gram_partials(L.gram, Q, m, ni, ldq, part, info, s)); th.end(0, s);
-  th.begin(1, s); CQR2_TRY(cqr2::launch_gram_reduce(L.gram, part, ni, W, n, info, s)); th.end(1, s);
-  th.begin(2, s); CQR2_TRY(cqr2::launch_cholinv(W, n, ni, R2, n, nullptr, 0, U2, L.np, info, ni, s)); th.end(2, s);
+  if (const int rc = cholinv(R2, U2, ni)) return rc;
   th.begin(4, s); CQR2_TRY(cqr2::launch_apply_rinv(Q, m, ni, ldq, U2, L.np, 1, Q, ldq, info, cus, s)); th.end(4, s);
   constexpr int kUp = cqr2::GEMM_A_UPPER | cqr2::GEMM_B_UPPER | cqr2::GEMM_C_UPPER;
   if (!shifted) {
-    // ---- R = R2 R1 (W is free again) ----
+    // ---- R = R2 R1 ----
     th.begin(5, s);
-    CQR2_TRY(cqr2::launch_gemm(0, 0, n, n, n, 1.0, R2, n, R1, n, 0.0, W, n, kUp, 1, nullptr, info, s));
-    CQR2_TRY(cqr2::launch_finalize_r(W, n, R, ldr, n, info, d_info, s));
+    CQR2_TRY(cqr2::launch_upper_product_final(R2, R1, n, R, ldr, info, d_info, s));
     th.end(5, s);
     return 0;
   }

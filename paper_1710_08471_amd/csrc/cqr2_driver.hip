@@ -205,6 +205,54 @@ hipError_t launch_finalize_r(const double* P, int64_t ldp, double* R, int64_t ld
   return hipGetLastError();
 }
 
+// R = triu(X Y) for upper-triangular X, Y (n x n, column-major, ld n); NaN
+// after a breakdown; the info word copied to user_info.  A workgroup per 16 x 16
+// tile of R: the tile's rows of X and columns of Y (k from 16 I to the tile's
+// last column) go through LDS, then each thread sums its entry over k = i..j in
+// ascending order.
+constexpr int kUpT = 16;
+constexpr int kUpMaxN = 128;
+
+__global__ __launch_bounds__(kUpT * kUpT) void k_upper_product_final(const double* __restrict__ X,
+                                                                     const double* __restrict__ Y, int n, double* R,
+                                                                     int64_t ldr, const int32_t* info,
+                                                                     int32_t* user_info) {
+  __shared__ double xs[kUpT][kUpMaxN];
+  __shared__ double ys[kUpMaxN][kUpT];
+  const int I = blockIdx.x, J = blockIdx.y;
+  const int ti = threadIdx.x % kUpT, tj = threadIdx.x / kUpT;
+  const int i = kUpT * I + ti, j = kUpT * J + tj;
+  const int32_t st = *info;
+  if (I == 0 && J == 0 && threadIdx.x == 0 && user_info != nullptr) *user_info = st;
+  const bool work = st == 0 && J >= I;
+  if (work) {
+    const int k0 = kUpT * I, k1 = min(n, kUpT * J + kUpT);
+    for (int e = threadIdx.x; e < kUpT * (k1 - k0); e += kUpT * kUpT) {
+      const int r = e % kUpT, k = k0 + e / kUpT;
+      const int row = kUpT * I + r, col = kUpT * J + r;
+      xs[r][k - k0] = row < n ? X[row + (int64_t)k * n] : 0.0;
+      ys[k - k0][r] = col < n ? Y[k + (int64_t)col * n] : 0.0;
+    }
+  }
+  __syncthreads();
+  if (i >= n || j >= n) return;
+  double v = 0.0;
+  if (work && i <= j) {
+    const int k0 = kUpT * I;
+    for (int k = i; k <= j; ++k) v = fma(xs[ti][k - k0], ys[k - k0][tj], v);
+  }
+  R[i + (int64_t)j * ldr] = st != 0 ? __builtin_nan("") : v;
+}
+
+hipError_t launch_upper_product_final(const double* X, const double* Y, int64_t n, double* R, int64_t ldr,
+                                      const int32_t* info, int32_t* user_info, hipStream_t s) {
+  if (n < 1 || n > kUpMaxN) return hipErrorInvalidValue;
+  const unsigned t = (unsigned)((n + kUpT - 1) / kUpT);
+  hipLaunchKernelGGL(k_upper_product_final, dim3(t, t), dim3(kUpT * kUpT), 0, s, X, Y, (int)n, R, ldr, info,
+                     user_info);
+  return hipGetLastError();
+}
+
 // ---- CholeskyQR2 for n > 128 ------------------------------------------------
 GeneralPlan plan_general(int64_t m, int64_t n, bool mixed, int depth) {
   GeneralPlan p{};

@@ -13,13 +13,20 @@ namespace cqr2 {
 
 constexpr int kGramSplits = 256;  // workgroups along m for large m (one per MI355X CU)
 
+// reset_info: this is the first kernel of a factorization -- no earlier
+// phase can have failed, and workgroup 0 clears the info word for the kernels
+// after it (no workgroup of this kernel reads it).
 template <int NG, int NW>
 __global__ __launch_bounds__(NW * 64) void k_gram_partials(const double* __restrict__ A, int64_t m, int n,
                                                            int64_t lda, int64_t stages, int64_t spw,
-                                                           double* __restrict__ partials,
-                                                           const int32_t* __restrict__ info) {
+                                                           double* __restrict__ partials, int32_t* info,
+                                                           int reset_info) {
   __shared__ double lds[2 * GramStage<NG, NW>::kBuf];
-  if (info != nullptr && *info != 0) return;
+  if (reset_info) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *info = 0;
+  } else if (info != nullptr && *info != 0) {
+    return;
+  }
   constexpr int nblk = NG * (NG + 1) / 2;
   const int64_t st0 = (int64_t)blockIdx.x * spw;
   const int64_t st1 = st0 + spw < stages ? st0 + spw : stages;
@@ -91,12 +98,14 @@ GramPlan plan_gram(int64_t m, int64_t n) {
 }
 
 hipError_t launch_gram_partials(const GramPlan& p, const double* A, int64_t m, int n, int64_t lda,
-                                double* partials, const int32_t* info, hipStream_t s) {
+                                double* partials, const int32_t* info, hipStream_t s, int32_t* reset_info) {
   dim3 grid(p.splits);
 #define CQR2_GRAM_CASE(NGV, NWV)                                                                     \
   case NGV:                                                                                          \
     hipLaunchKernelGGL((k_gram_partials<NGV, NWV>), grid, dim3(NWV * 64), 0, s, A, m, n, lda,        \
-                       p.stages, p.stages_per_wg, partials, info);                                   \
+                       p.stages, p.stages_per_wg, partials,                                          \
+                       reset_info != nullptr ? reset_info : const_cast<int32_t*>(info),              \
+                       reset_info != nullptr ? 1 : 0);                                               \
     break;
   switch (p.ng) {
     CQR2_GRAM_CASE(1, 1)

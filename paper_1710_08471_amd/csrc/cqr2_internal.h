@@ -37,8 +37,11 @@ struct GramPlan {
 GramPlan plan_gram(int64_t m, int64_t n);
 
 // Partial Grams of A (m x n, lda) into `partials` (plan.partial_bytes).
+// reset_info != nullptr: the first kernel of a factorization; it clears
+// *reset_info (and reads no info word).
 hipError_t launch_gram_partials(const GramPlan& p, const double* A, int64_t m, int n, int64_t lda,
-                                double* partials, const int32_t* info, hipStream_t s);
+                                double* partials, const int32_t* info, hipStream_t s,
+                                int32_t* reset_info = nullptr);
 // Fixed-order sum of the partials into the full symmetric W (n x n, ldw).
 hipError_t launch_gram_reduce(const GramPlan& p, const double* partials, int n, double* W, int64_t ldw,
                               const int32_t* info, hipStream_t s);
@@ -53,6 +56,7 @@ int padded_order(int64_t n);
 hipError_t launch_cholinv(const double* W, int64_t ldw, int n, double* R, int64_t ldr, double* Rinv,
                           int64_t ldri, double* Upad, int np, int32_t* info, int info_offset,
                           hipStream_t s);
+
 
 // ---- Q = A U ---------------------------------------------------------------
 // U upper triangular n x n, element (i, j) at U[i*urs + j*ucs] (only i <= j < n
@@ -140,6 +144,11 @@ hipError_t cholinv_recursive(double* W, int64_t ldw, int64_t n, double* R, int64
 // R = triu(P), or NaN after a breakdown; copies the info word to user_info.
 hipError_t launch_finalize_r(const double* P, int64_t ldp, double* R, int64_t ldr, int64_t n, const int32_t* info,
                              int32_t* user_info, hipStream_t s);
+// R = triu(X Y) for upper-triangular n x n X, Y (ld n, n <= 128), NaN after a
+// breakdown, info copied to user_info: the last step of Algorithm 5 in one
+// launch.
+hipError_t launch_upper_product_final(const double* X, const double* Y, int64_t n, double* R, int64_t ldr,
+                                      const int32_t* info, int32_t* user_info, hipStream_t s);
 
 // W(j, i) = W(i, j) for i > j.
 hipError_t launch_mirror_lower(double* W, int64_t ldw, int64_t n, hipStream_t s);
