@@ -10,11 +10,15 @@ command which produced the raw data:
              runs of the same program: HBM bytes per dispatch of each kernel,
              scaled by what the same counters read for a device copy of known
              size in that program (the calibration).
+  mfma    -- from ``rocprofv3 --pmc MfmaUtil MfmaFlopsF64 MfmaFlopsF32``: per
+             kernel the matrix-core FLOPs per dispatch (FP64 and FP32) and the
+             fraction of SIMD cycles the matrix cores were busy.
 
 Usage:
   python -m paper_1710_08471_amd.profiling stats DIR --command CMD --out FILE
   python -m paper_1710_08471_amd.profiling traffic --fetch DIR --write DIR \\
       --copy-bytes N --command-fetch CMD --command-write CMD --out-json F --out-txt F
+  python -m paper_1710_08471_amd.profiling mfma DIR --command CMD --out FILE
 """
 from __future__ import annotations
 
@@ -166,6 +170,33 @@ def traffic_report(fetch_dir: str, write_dir: str, copy_bytes: int, cmd_fetch: s
     return data, "\n".join(lines) + "\n"
 
 
+def mfma_report(dirpath: str, command: str) -> str:
+    path = _find(dirpath, "_counter_collection.csv")
+    vals = collections.defaultdict(lambda: collections.defaultdict(list))
+    for r in csv.DictReader(open(path)):
+        name = short_name(r["Kernel_Name"])
+        if not name.startswith("k_"):
+            continue
+        vals[name][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    lines = [
+        "Matrix-core work per dispatch from rocprofv3 derived counters",
+        f"command: {command}",
+        "MfmaFlopsF64/F32 = SQ_INSTS_VALU_MFMA_MOPS_F64/F32 x 512; MfmaUtil = SQ_VALU_MFMA_BUSY_CYCLES /",
+        "(GRBM_GUI_ACTIVE x SIMDs), in percent, over the dispatch.",
+        "",
+        f"{'kernel':<40} {'disp':>5} {'GFLOP_f64':>11} {'GFLOP_f32':>11} {'mfma_busy_%':>12}",
+    ]
+    for name in sorted(vals):
+        v = vals[name]
+        def mean(c):
+            x = v.get(c, [])
+            return sum(x) / len(x) if x else float("nan")
+        disp = max(len(x) for x in v.values())
+        lines.append(f"{name[:40]:<40} {disp:>5} {mean('MfmaFlopsF64') / 1e9:>11.3f} "
+                     f"{mean('MfmaFlopsF32') / 1e9:>11.3f} {mean('MfmaUtil'):>12.1f}")
+    return "\n".join(lines) + "\n"
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -181,7 +212,17 @@ def main():
     t.add_argument("--command-write", required=True)
     t.add_argument("--out-json", required=True)
     t.add_argument("--out-txt", required=True)
+    mf = sub.add_parser("mfma")
+    mf.add_argument("dir")
+    mf.add_argument("--command", required=True)
+    mf.add_argument("--out", required=True)
     a = ap.parse_args()
+    if a.cmd == "mfma":
+        text = mfma_report(a.dir, a.command)
+        with open(a.out, "w") as f:
+            f.write(text)
+        print(text)
+        return
     if a.cmd == "stats":
         text = stats_report(a.dir, a.command)
         with open(a.out, "w") as f:
