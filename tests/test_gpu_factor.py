@@ -60,6 +60,32 @@ def test_factor_named_1Mx128_workload_full_size(gpu_lib):
     check_against_oracle(a, q, r, q_ref, r_ref)
 
 
+@pytest.mark.slow
+def test_factor_named_65536x4096_workload_full_size(gpu_lib):
+    """The 65536 x 4096 problem (tiled Gram, recursive CholInv, column-tiled
+    Q) in the benchmark's launch configuration, against the oracle on the same
+    bytes: R and Q element by element.  Orthogonality and the residual at this
+    size are checked on the device with torch's FP64 products (plain library
+    GEMMs, not the path under test)."""
+    import torch
+    a = workload_matrix("rect_65536x4096")
+    ad = to_dev(a)
+    qd, rd = gpu_lib.factor(ad)
+    q, r = to_host(qd), to_host(rd)
+    q_ref, r_ref = oracle.cqr2(a)
+    assert np.array_equal(r, np.triu(r)) and np.all(np.diag(r) > 0)
+    nr = np.linalg.norm(r_ref)
+    assert oracle.rel_fro(r, r_ref) <= TOL_R
+    assert np.max(np.abs(r - r_ref)) <= TOL_R * nr
+    assert np.max(np.abs(q - q_ref)) <= TOL_Q
+    qt = qd.contiguous()
+    g = qt.t().contiguous() @ qt
+    g.diagonal().sub_(1.0)
+    assert float(torch.linalg.norm(g)) <= TOL_ORTH
+    res = ad.contiguous() - qt @ rd.contiguous()
+    assert float(torch.linalg.norm(res) / torch.linalg.norm(ad.contiguous())) <= TOL_RES
+
+
 def test_factor_lda_padding_and_unaligned(gpu_lib):
     m, n = 9001, 50
     a = gdv_matrix(m, n, 1e4, 21)
