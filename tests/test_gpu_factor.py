@@ -86,6 +86,35 @@ def test_factor_named_65536x4096_workload_full_size(gpu_lib):
     assert float(torch.linalg.norm(res) / torch.linalg.norm(ad.contiguous())) <= TOL_RES
 
 
+@pytest.mark.slow
+def test_factor_largest_n(gpu_lib):
+    """n = CQR2_MAX_N (16384), nearly square: too large for the oracle, so the
+    properties that hold at any size are checked on the device -- upper
+    triangular R with a positive diagonal, ||QᵀQ - I||_F and ||A - QR||_F /
+    ||A||_F within the first-order bounds (m n + n (n+1)) u and n^2 u of
+    CholeskyQR2 -- plus bitwise determinism."""
+    import torch
+    n = 16384
+    m = n + 64
+    g = torch.Generator(device="cuda")
+    g.manual_seed(901)
+    scale = torch.logspace(0, -2, n, dtype=torch.float64, device="cuda")
+    ad = (torch.randn((n, m), generator=g, dtype=torch.float64, device="cuda") * scale[:, None]).t()
+    q1, r1 = gpu_lib.factor(ad)
+    q2, r2 = gpu_lib.factor(ad)
+    torch.cuda.synchronize()
+    assert torch.equal(q1, q2) and torch.equal(r1, r2)
+    u = 2.0 ** -53
+    assert bool(torch.all(torch.diagonal(r1) > 0))
+    assert bool(torch.all(torch.tril(r1, -1) == 0))
+    qt = q1.contiguous()
+    gram = qt.t().contiguous() @ qt
+    gram.diagonal().sub_(1.0)
+    assert float(torch.linalg.norm(gram)) <= (m * n + n * (n + 1)) * u
+    res = ad.contiguous() - qt @ r1.contiguous()
+    assert float(torch.linalg.norm(res) / torch.linalg.norm(ad.contiguous())) <= n * n * u
+
+
 def test_factor_lda_padding_and_unaligned(gpu_lib):
     m, n = 9001, 50
     a = gdv_matrix(m, n, 1e4, 21)
