@@ -49,7 +49,16 @@ __global__ __launch_bounds__(256) void k_gram_reduce(const double* __restrict__ 
   double v = 0.0;
   if (e < total) {
     const int s0 = (splits * sub) / 8, s1 = (splits * (sub + 1)) / 8;
-    for (int s = s0; s < s1; ++s) v += part[(int64_t)s * total + e];
+    // in split order; the loads go out eight at a time
+    int s = s0;
+    for (; s + 8 <= s1; s += 8) {
+      double x[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) x[j] = part[(int64_t)(s + j) * total + e];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) v += x[j];
+    }
+    for (; s < s1; ++s) v += part[(int64_t)s * total + e];
   }
   red[sub][lane] = v;
   __syncthreads();
