@@ -1,5 +1,6 @@
-// Internal launch interface between the C ABI (cqr2_api.hip) and the kernels
-// (cqr2_gram.hip, cqr2_cholinv.hip, cqr2_apply.hip, cqr2_gemm.hip, cqr2_driver.hip).
+// Internal launch interface between the C ABI (cqr2_api.hip, cqr2_serve.hip)
+// and the kernels (cqr2_gram.hip, cqr2_cholinv.hip, cqr2_apply.hip,
+// cqr2_gemm.hip, cqr2_wide.hip, cqr2_step.hip, cqr2_driver.hip).
 // Not installed; no torch types anywhere.
 #pragma once
 #include <hip/hip_runtime.h>
