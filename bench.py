@@ -121,10 +121,10 @@ def cpu_baseline(a, budget_s: float):
 
 
 # Served stream (2000 requests of uneven shape, Poisson arrivals at a fixed
-# rate); the rate is pinned at about half the measured closed-loop capacity.
+# rate); the rate is pinned well below the measured closed-loop capacity.
 SERVE_REQUESTS = 2000
 SERVE_SEED = 5
-SERVE_RATE = 2500.0            # requests per second (open loop), about 0.45 of the closed-loop capacity
+SERVE_RATE = 2500.0            # requests per second (open loop), about 0.3 of the closed-loop capacity
 SERVE_ARENA = 16 << 30         # workspace arena of the server, bytes
 SERVE_BUDGET = 64 << 30        # in-flight footprint budget (A, Q, R, workspace), bytes
 SERVE_SLOTS = 256

@@ -190,7 +190,10 @@ struct cqr2_server {
     std::vector<size_t> offs;
   };
 
-  static constexpr int kLargeStreams = 4;
+  // Three streams for n > 128 requests: with the step stream that makes four,
+  // HIP's default number of hardware queues per process, so the steps never
+  // share a queue with a large request's kernels.
+  static constexpr int kLargeStreams = 3;
   hipStream_t stream = nullptr;              // steps
   hipStream_t large[kLargeStreams] = {};     // n > 128 requests, round robin
   int large_next = 0;
