@@ -224,10 +224,11 @@ int cqr2_factor_batched(const cqr2_problem* probs, int32_t count, void* work, si
  * launches ONE multi-problem kernel that advances every active n <= 128
  * request by one phase, so requests admitted at different times share each
  * launch and a request finishes six steps after its admission.  Requests with
- * n > 128 run the tiled path on one of three further streams of the server
- * (round robin) as soon as they are admitted, overlapping the steps; with
- * the step stream that is four streams, HIP's default number of hardware
- * queues per process.  Nothing blocks on the GPU except when
+ * n > 128 run the tiled path on further streams of the server (round
+ * robin) as soon as they are admitted, overlapping the steps.  There are one
+ * fewer of them than the process's hardware queues (the GPU_MAX_HW_QUEUES
+ * environment variable that HIP reads, default 4: three streams), so the
+ * step stream keeps a queue of its own.  Nothing blocks on the GPU except when
  * the host runs more than a few steps ahead (pinned task-table ring).
  * Completion times are HIP event times in milliseconds since the last
  * cqr2_server_clock call.  A, Q and R stay owned by the caller and must stay

@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -190,12 +191,14 @@ struct cqr2_server {
     std::vector<size_t> offs;
   };
 
-  // Three streams for n > 128 requests: with the step stream that makes four,
-  // HIP's default number of hardware queues per process, so the steps never
-  // share a queue with a large request's kernels.
-  static constexpr int kLargeStreams = 3;
-  hipStream_t stream = nullptr;              // steps
-  hipStream_t large[kLargeStreams] = {};     // n > 128 requests, round robin
+  // Streams for n > 128 requests: one fewer than the process's hardware
+  // queues (GPU_MAX_HW_QUEUES, HIP's default 4), so that with the step stream
+  // every stream has a queue of its own and the steps never wait behind a
+  // large request's kernels.
+  static constexpr int kMaxLargeStreams = 31;
+  int n_large = 3;
+  hipStream_t stream = nullptr;                 // steps
+  hipStream_t large[kMaxLargeStreams] = {};     // n > 128 requests, round robin
   int large_next = 0;
   char* arena_base = nullptr;
   Arena arena;
@@ -261,7 +264,7 @@ struct cqr2_server {
         const cqr2_problem& p = r.p;
         const cqr2::GeneralPlan plan = cqr2::plan_general(p.m, p.n, false);
         hipStream_t ls = large[large_next];
-        large_next = (large_next + 1) % kLargeStreams;
+        large_next = (large_next + 1) % n_large;
         char* ws = arena_base + off;
         hipError_t e = cqr2::factor_general(p.A, p.m, p.n, p.lda, p.Q, p.ldq, p.R, p.ldr, ws, plan, false,
                                             p.d_info, ls, cqr2::TimerHook{});
@@ -423,8 +426,14 @@ int cqr2_server_create(size_t arena_bytes, size_t footprint_budget, int32_t max_
   };
   if (hipMalloc((void**)&sv->arena_base, arena_bytes) != hipSuccess) return fail(CQR2_ERR_HIP);
   sv->arena.reset(arena_bytes);
-  for (auto& ls : sv->large)
-    if (hipStreamCreateWithFlags(&ls, hipStreamNonBlocking) != hipSuccess) return fail(CQR2_ERR_HIP);
+  int hw_queues = 4;  // HIP's default hardware queues per process
+  if (const char* e = std::getenv("GPU_MAX_HW_QUEUES")) {
+    const int v = std::atoi(e);
+    if (v > 0) hw_queues = v;
+  }
+  sv->n_large = std::min(std::max(hw_queues - 1, 1), cqr2_server::kMaxLargeStreams);
+  for (int i = 0; i < sv->n_large; ++i)
+    if (hipStreamCreateWithFlags(&sv->large[i], hipStreamNonBlocking) != hipSuccess) return fail(CQR2_ERR_HIP);
   const size_t tb = align_up((size_t)max_active * sizeof(cqr2::StepTask));
   for (int i = 0; i < 8; ++i) {
     char* d = nullptr;
