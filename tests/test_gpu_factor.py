@@ -177,6 +177,25 @@ def test_factor_breakdown_reports_column(gpu_lib, j):
     assert e.value.j == j + 1
 
 
+@pytest.mark.parametrize("bad", [float("nan"), float("inf"), float("-inf")])
+@pytest.mark.parametrize("n,j", [(64, 17), (128, 100), (200, 150)])
+def test_factor_nonfinite_input_reports_column(gpu_lib, bad, n, j):
+    """A NaN or infinite entry in column j of A makes row and column j of the
+    Gram non-finite; the columns before j factor normally, and pivot j is NaN
+    (inf - inf), so pass 1 reports column j + 1 and R is all NaN.  n = 200
+    runs the tiled path, where j falls in the second half of the recursion."""
+    import torch
+    a = gdv_matrix(3000, n, 1e3, 900 + j)
+    a[1234, j] = bad
+    with np.errstate(invalid="ignore", over="ignore"), pytest.raises(oracle.NotSPD) as e:
+        oracle.cqr2(a)
+    assert e.value.j == j + 1
+    info = torch.zeros((1,), dtype=torch.int32, device="cuda")
+    q, r = gpu_lib.factor_ex(to_dev(a), info=info)
+    assert int(info.item()) == j + 1
+    assert np.all(np.isnan(to_host(r)))
+
+
 def test_factor_breakdown_without_info_gives_nan_r(gpu_lib):
     a = gdv_matrix(3000, 20, 10.0, 27)
     a[:, 4] = 0.0              # exactly rank deficient: pivot 5 is exactly zero
