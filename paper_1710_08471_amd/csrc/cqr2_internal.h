@@ -124,8 +124,8 @@ hipError_t launch_tall_gemm_f32(const double* A, int64_t m, int n, int64_t lda, 
 
 // ---- Gram for n > 256 by 128 x 128 tiles --------------------------------------
 struct SyrkPlan {
-  int npairs = 0, splits = 0;             // lower tile pairs, row splits
-  int64_t stages = 0, stages_per_wg = 0;  // 32-row stages
+  int npairs = 0, splits = 0;             // lower 128 x 256 tiles, row splits
+  int64_t stages = 0, stages_per_wg = 0;  // 16-row chunks
   size_t partial_bytes = 0;
 };
 SyrkPlan plan_syrk(int64_t m, int64_t n);

@@ -240,151 +240,209 @@ hipError_t launch_gram_wide(const WideGramPlan& p, int a_f32, const void* A, int
 }
 
 // ============================================================================
-// Gram for n > 256, by 128 x 128 tiles of its lower triangle.
+// Gram for n > 256 (Syrk; Algorithm 4 step 1), by 128 x 256 tiles of its
+// lower triangle, on MFMA 4x4x4 in the manner of the tall kernel below.
 //
-// Workgroup (tile pair (I, J), I >= J; row split s) streams the two column
-// panels A(:, 128 I ..) and A(:, 128 J ..) of its rows through LDS in 32-row
-// stages (direct 16-byte copies, the swizzle of the n <= 256 kernel, double
-// buffered: 2 x 2 x 32 KB; a diagonal pair loads one panel) and accumulates
-// W(128 I + .., 128 J + ..) with MFMA 16x16x4: wave w owns the 16 rows
-// 16 w .. of the tile and its eight 16 x 16 tiles (the lower ones only on a
-// diagonal pair).  Partial tiles are summed over the row splits in a fixed
+// Workgroup (tile t, row split s) owns W(128 ti .., 256 tj ..) for the lower
+// tiles (256 tj <= 128 ti + 127, ordered by ti then tj) and the 16-row chunks
+// of its split.  Each chunk of the two column panels A(rows, 128 ti ..) and
+// A(rows, 256 tj ..) is copied straight from global memory into a ring of
+// three LDS buffers (16 KB + 32 KB; two chunks in flight while one is
+// multiplied); each wave waits for its own copies by count, then a barrier
+// publishes them.  In LDS a panel is column-major, 16 values per column, the
+// k index of column c stored XOR 2 ((c >> 1) & 7) (the copies gather their
+// source rows to match), so a fragment's 16 columns spread over the banks.
+// Wave w owns the 64 x 64 block (64 (w / 4), 64 (w % 4)) of the tile: MFMA
+// 4x4x4 with lane l holding A(k + l / 16, i + l % 16) and A(k + l / 16,
+// j + l % 4), output lane l is W(i + 4 ((l >> 2) & 3) + l / 16, j + l % 4).
+// Blocks and column groups wholly above the diagonal are skipped.  Columns
+// past n are read from column n - 1 (finite data in outputs never written);
+// rows past m are zero.  Partial tiles are summed over the splits in a fixed
 // order by k_syrk_reduce.
 // ============================================================================
-constexpr int kSyT = 128;                   // output tile (columns per panel)
-constexpr int kSyBuf = kSyT * kWideRows;    // doubles per panel stage
-constexpr int kSyTile = kSyT * kSyT;        // doubles per partial tile
+constexpr int kSyI = 128, kSyJ = 256, kSyK = 16, kSyBufs = 3;
+constexpr int kSyWave = 64 * 64;       // doubles of one wave's partial block
+constexpr int kSyTile = 8 * kSyWave;   // doubles of one workgroup's partial tile
 
-__device__ __forceinline__ void syrk_pair(int t, int& I, int& J) {
-  int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-  while (i * (i + 1) / 2 > t) --i;
-  while ((i + 1) * (i + 2) / 2 <= t) ++i;
-  I = i;
-  J = t - i * (i + 1) / 2;
+// XOR on the k slots of column c in LDS (even: the 16-byte copies keep their pairs)
+__device__ __forceinline__ int syrk_swz(int c) { return 2 * ((c >> 1) & 7); }
+
+// lower tile t -> (ti, tj): block row ti holds ti / 2 + 1 tiles, so the
+// tiles of block rows 2a and 2a + 1 start at a (a + 1) and (a + 1)^2
+__device__ __forceinline__ void syrk_tile(int t, int& ti, int& tj) {
+  int a = (int)((sqrt(4.0 * t + 1.0) - 1.0) * 0.5);
+  while (a * (a + 1) > t) --a;
+  while ((a + 1) * (a + 2) <= t) ++a;
+  if (t < (a + 1) * (a + 1)) {
+    ti = 2 * a;
+    tj = t - a * (a + 1);
+  } else {
+    ti = 2 * a + 1;
+    tj = t - (a + 1) * (a + 1);
+  }
+}
+
+static int syrk_ntiles(int64_t n) {
+  const int64_t TI = (n + kSyI - 1) / kSyI;
+  int64_t c = 0;
+  for (int64_t ti = 0; ti < TI; ++ti) c += (ti >> 1) + 1;
+  return (int)c;
 }
 
 __global__ __launch_bounds__(512, 1) void k_syrk_tile(const double* __restrict__ A, int64_t m, int n, int64_t lda,
-                                                      int64_t stages, int64_t spw, double* __restrict__ partials,
-                                                      int npairs, const int32_t* __restrict__ info) {
-  __shared__ __attribute__((aligned(16))) double lds[2 * 2 * kSyBuf];
+                                                      int64_t chunks_per_split, double* __restrict__ partials,
+                                                      int ntiles, const int32_t* __restrict__ info) {
+  constexpr int kIBytes = kSyK * kSyI * 8, kJBytes = kSyK * kSyJ * 8, kBufBytes = kIBytes + kJBytes;
+  constexpr int kPerChunk = 6;  // copies per wave and chunk: 2 of the I panel, 4 of the J panel
+  __shared__ __attribute__((aligned(16))) char smem[kSyBufs * kBufBytes];
   if (info != nullptr && *info != 0) return;
-  int TI, TJ;
-  syrk_pair(blockIdx.x, TI, TJ);
-  const bool diag = TI == TJ;
-  const int64_t st0 = (int64_t)blockIdx.y * spw;
-  const int64_t st1 = st0 + spw < stages ? st0 + spw : stages;
+  int ti, tj;
+  syrk_tile((int)blockIdx.x, ti, tj);
+  const int I0 = kSyI * ti, J0 = kSyJ * tj;
+  const int64_t total_chunks = (m + kSyK - 1) / kSyK;
+  const int64_t cb = (int64_t)blockIdx.y * chunks_per_split;
+  const int64_t ce = cb + chunks_per_split < total_chunks ? cb + chunks_per_split : total_chunks;
+  const int nch = ce > cb ? (int)(ce - cb) : 0;
   const int tid = threadIdx.x, lane = tid & 63;
-  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int colI = kSyT * TI, colJ = kSyT * TJ;
-  const bool direct_ok = (((uintptr_t)A & 15u) == 0) && ((lda & 1) == 0);
-
-  // columns >= n are never loaded: zero them in every buffer once
-  for (int e = tid; e < 4 * kSyBuf; e += 512) {
-    const int panel = (e / kSyBuf) & 1;  // buffers: [stage 0: I, J][stage 1: I, J]
-    const int c = (e % kSyBuf) / kWideRows;
-    if ((panel == 0 ? colI : colJ) + c >= n) lds[e] = 0.0;
-  }
-  auto fill_panel = [&](int64_t st, int col0, double* buf) {
-    const int64_t row0 = st * kWideRows;
-    if (direct_ok && row0 + kWideRows <= m) {
-      const int sub = lane >> 4, lrow = 2 * (lane & 15);
-      for (int p = w; p < kSyT / 4; p += 8) {
-        const int c = 4 * p + sub;
-        if (col0 + c < n) {
-          const int grow = lrow ^ ((c & 15) << 1);
-          __builtin_amdgcn_global_load_lds((const void*)(A + row0 + grow + (int64_t)(col0 + c) * lda),
-                                           (__attribute__((address_space(3))) void*)(buf + 4 * p * kWideRows), 16, 0,
-                                           0);
-        }
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wr = 64 * (wave >> 2), wc = 64 * (wave & 3);
+  const bool aligned = (((uintptr_t)A & 15u) == 0) && ((lda & 1) == 0);
+  auto ibuf = [&](int b) { return (double*)(smem + b * kBufBytes); };
+  auto jbuf = [&](int b) { return (double*)(smem + b * kBufBytes + kIBytes); };
+  auto direct_chunk = [&](int p) { return aligned && (cb + p + 1) * kSyK <= m; };
+  auto issue = [&](int p) {
+    const int b = p % kSyBufs;
+    const int64_t row0 = (cb + p) * kSyK;
+    double* Ib = ibuf(b);
+    double* Jb = jbuf(b);
+    if (direct_chunk(p)) {
+      // one copy: 8 columns x 16 rows; lane i -> column 8 t + (i >> 3), k slots 2 (i & 7), +1
+      const int sub = lane >> 3, kp = 2 * (lane & 7);
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int it = 2 * wave + t, c = 8 * it + sub;
+        const int col = I0 + c < n ? I0 + c : n - 1;
+        __builtin_amdgcn_global_load_lds((const void*)(A + row0 + (kp ^ syrk_swz(c)) + (int64_t)col * lda),
+                                         (__attribute__((address_space(3))) void*)(Ib + 8 * it * kSyK), 16, 0, 0);
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int it = 4 * wave + t, c = 8 * it + sub;
+        const int col = J0 + c < n ? J0 + c : n - 1;
+        __builtin_amdgcn_global_load_lds((const void*)(A + row0 + (kp ^ syrk_swz(c)) + (int64_t)col * lda),
+                                         (__attribute__((address_space(3))) void*)(Jb + 8 * it * kSyK), 16, 0, 0);
       }
     } else {
-      for (int e = tid; e < kSyBuf; e += 512) {
-        const int c = e / kWideRows, r = e % kWideRows;
-        const int64_t row = row0 + r;
-        buf[wide_pos(c, r)] = (row < m && col0 + c < n) ? A[row + (int64_t)(col0 + c) * lda] : 0.0;
+      for (int e = tid; e < kSyK * (kSyI + kSyJ); e += 512) {
+        const int c = e / kSyK, k = e % kSyK;
+        const bool in_i = c < kSyI;
+        const int cc = in_i ? c : c - kSyI;
+        int col = (in_i ? I0 : J0) + cc;
+        col = col < n ? col : n - 1;
+        const int64_t r = row0 + k;
+        (in_i ? Ib : Jb)[cc * kSyK + (k ^ syrk_swz(cc))] = r < m ? A[r + (int64_t)col * lda] : 0.0;
       }
     }
-  };
-  auto fill = [&](int64_t st, int b) {
-    fill_panel(st, colI, lds + (2 * b) * kSyBuf);
-    if (!diag) fill_panel(st, colJ, lds + (2 * b + 1) * kSyBuf);
   };
 
-  wd4 acc[8];
+  double acc[4][16];
 #pragma unroll
-  for (int c = 0; c < 8; ++c) acc[c] = wd4{0.0, 0.0, 0.0, 0.0};
-  __syncthreads();
-  if (st0 < st1) fill(st0, 0);
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-  const int fc = lane & 15, fk = lane >> 4;
-  const bool row_live = colI + 16 * w < n;
-  for (int64_t st = st0; st < st1; ++st) {
-    const int b = (int)((st - st0) & 1);
-    const double* bI = lds + (2 * b) * kSyBuf;
-    const double* bJ = diag ? bI : lds + (2 * b + 1) * kSyBuf;
-    if (st + 1 < st1) fill(st + 1, b ^ 1);
-    if (row_live) {
-#pragma unroll 1
-      for (int k0 = 0; k0 < kWideRows; k0 += 4) {
-        const double fi = bI[wide_pos(16 * w + fc, k0 + fk)];
-        double fj[8];
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int c = 0; c < 8; ++c) fj[c] = bJ[wide_pos(16 * c + fc, k0 + fk)];
+    for (int b = 0; b < 16; ++b) acc[a][b] = 0.0;
+  // this wave's 64 x 64 block: nothing to do above the diagonal or past n
+  const bool live = (J0 + wc <= I0 + wr + 63) && (I0 + wr < n) && (J0 + wc < n);
+  if (nch > 0) issue(0);
+  if (nch > 1) issue(1);
+  const int ar = lane & 15, ak = lane >> 4, bc = lane & 3;
+  for (int p = 0; p < nch; ++p) {
+    if (p + 1 < nch && direct_chunk(p + 1)) wait_vmcnt<kPerChunk>();
+    else wait_vmcnt<0>();
+    lds_barrier();
+    if (p + 2 < nch) issue(p + 2);
+    const double* Ib = ibuf(p % kSyBufs);
+    const double* Jb = jbuf(p % kSyBufs);
+    if (live) {
 #pragma unroll
-        for (int c = 0; c < 8; ++c)
-          if ((!diag || c <= w) && colJ + 16 * c < n)  // uniform
-            acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(fi, fj[c], acc[c], 0, 0, 0);
+      for (int ks = 0; ks < kSyK; ks += 4) {
+        const int kk = ks + ak;
+        double a[4];
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) {
+          const int c = wr + 16 * rt + ar;
+          a[rt] = Ib[c * kSyK + (kk ^ syrk_swz(c))];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (J0 + wc + 16 * q <= I0 + wr + 63) {  // uniform: the column group reaches the lower triangle
+            double b[4];
+#pragma unroll
+            for (int c4 = 0; c4 < 4; ++c4) {
+              const int c = wc + 16 * q + 4 * c4 + bc;
+              b[c4] = Jb[c * kSyK + (kk ^ syrk_swz(c))];
+            }
+#pragma unroll
+            for (int c4 = 0; c4 < 4; ++c4)
+#pragma unroll
+              for (int rt = 0; rt < 4; ++rt)
+                acc[rt][4 * q + c4] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[rt], b[c4], acc[rt][4 * q + c4], 0, 0, 0);
+          }
+        }
       }
     }
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
   }
-  double* out = partials + ((int64_t)blockIdx.y * npairs + blockIdx.x) * kSyTile;
+  // lane-major partial block: entry (rt, cg) of lane l at (rt 16 + cg) 64 + l
+  double* out = partials + ((int64_t)blockIdx.y * ntiles + blockIdx.x) * kSyTile + wave * kSyWave;
 #pragma unroll
-  for (int c = 0; c < 8; ++c)
+  for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) out[((w * 8 + c) * 4 + r) * 64 + lane] = acc[c][r];
+    for (int cg = 0; cg < 16; ++cg) out[(rt * 16 + cg) * 64 + lane] = acc[rt][cg];
 }
 
-// W(lower) = sum over the splits, in split order, of the partial tiles.
-__global__ __launch_bounds__(256) void k_syrk_reduce(const double* __restrict__ part, int splits, int npairs, int n,
+// W(i, j), i >= j: the partial tiles summed in split order.
+__global__ __launch_bounds__(256) void k_syrk_reduce(const double* __restrict__ part, int splits, int ntiles, int n,
                                                      double* __restrict__ W, int64_t ldw,
                                                      const int32_t* __restrict__ info) {
   if (info != nullptr && *info != 0) return;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= (int64_t)npairs * kSyTile) return;
-  const int pair = (int)(e / kSyTile), x = (int)(e % kSyTile);
-  int TI, TJ;
-  syrk_pair(pair, TI, TJ);
-  const int w = x >> 11, c = (x >> 8) & 7, r = (x >> 6) & 3, l = x & 63;
-  const int row = kSyT * TI + 16 * w + 4 * r + (l >> 4), col = kSyT * TJ + 16 * c + (l & 15);
-  if (row >= n || col > row) return;
+  if (e >= (int64_t)ntiles * kSyTile) return;
+  const int tile = (int)(e / kSyTile), rem = (int)(e % kSyTile);
+  int ti, tj;
+  syrk_tile(tile, ti, tj);
+  const int wave = rem / kSyWave, x = rem % kSyWave;
+  const int lane = x & 63, cg = (x >> 6) & 15, rt = x >> 10;
+  const int i = kSyI * ti + 64 * (wave >> 2) + 16 * rt + 4 * ((lane >> 2) & 3) + (lane >> 4);
+  const int j = kSyJ * tj + 64 * (wave & 3) + 4 * cg + (lane & 3);
+  if (i >= n || j > i) return;
   double v = 0.0;
-  for (int s = 0; s < splits; ++s) v += part[(int64_t)s * npairs * kSyTile + e];
-  W[row + (int64_t)col * ldw] = v;
+  for (int s = 0; s < splits; ++s) v += part[(int64_t)s * ntiles * kSyTile + e];
+  W[i + (int64_t)j * ldw] = v;
 }
 
+// Splits fill the device several times over (about 4096 workgroups, one per
+// CU at a time), with at least 32 chunks (512 rows) each and at most 1 GiB of
+// partial tiles.
 SyrkPlan plan_syrk(int64_t m, int64_t n) {
   SyrkPlan p{};
-  const int t = (int)((n + kSyT - 1) / kSyT);
-  p.npairs = t * (t + 1) / 2;
-  p.stages = m > 0 ? (m + kWideRows - 1) / kWideRows : 1;
-  // at least four workgroups per CU of a 256-CU device, at least 64 stages (2048 rows) each
-  int64_t s = (4 * 256 + p.npairs - 1) / p.npairs;
-  const int64_t smax = p.stages / 64 > 0 ? p.stages / 64 : 1;
-  if (s > smax) s = smax;
+  p.npairs = syrk_ntiles(n);
+  p.stages = m > 0 ? (m + kSyK - 1) / kSyK : 0;
+  const int64_t tile_bytes = (int64_t)kSyTile * sizeof(double);
+  int64_t s = (4096 + p.npairs - 1) / p.npairs;
+  const int64_t by_rows = p.stages / 32 > 0 ? p.stages / 32 : 1;
+  const int64_t by_bytes = ((int64_t)1 << 30) / (tile_bytes * p.npairs) > 0 ? ((int64_t)1 << 30) / (tile_bytes * p.npairs) : 1;
+  if (s > by_rows) s = by_rows;
+  if (s > by_bytes) s = by_bytes;
   if (s < 1) s = 1;
-  p.stages_per_wg = (p.stages + s - 1) / s;
-  p.splits = (int)((p.stages + p.stages_per_wg - 1) / p.stages_per_wg);
-  p.partial_bytes = (size_t)p.splits * p.npairs * kSyTile * sizeof(double);
+  p.stages_per_wg = p.stages > 0 ? (p.stages + s - 1) / s : 1;
+  p.splits = p.stages > 0 ? (int)((p.stages + p.stages_per_wg - 1) / p.stages_per_wg) : 1;
+  p.partial_bytes = (size_t)p.splits * p.npairs * tile_bytes;
   return p;
 }
 
 hipError_t launch_syrk(const SyrkPlan& p, const double* A, int64_t m, int n, int64_t lda, double* partials,
                        double* W, int64_t ldw, const int32_t* info, hipStream_t s) {
-  hipLaunchKernelGGL(k_syrk_tile, dim3(p.npairs, p.splits), dim3(512), 0, s, A, m, n, lda, p.stages, p.stages_per_wg,
-                     partials, p.npairs, info);
+  hipLaunchKernelGGL(k_syrk_tile, dim3(p.npairs, p.splits), dim3(512), 0, s, A, m, n, lda, p.stages_per_wg, partials,
+                     p.npairs, info);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t total = (int64_t)p.npairs * kSyTile;
