@@ -8,6 +8,10 @@
 //                   128 x 256 output tile per workgroup, A read once; FP64
 //                   arithmetic, or FP32 products and sums into an FP32 Q
 //                   (pass 1 of the mixed-precision form).
+// and, for any n > 256, the Gram by 128 x 256 tiles of its lower triangle:
+//   k_syrk_tile     partial tiles over row splits, MFMA 4x4x4 fed the way
+//                   k_tall is fed;
+//   k_syrk_reduce   fixed-order sum of the partial tiles into W (lower).
 #include "cqr2_internal.h"
 
 #include <hip/hip_runtime.h>
