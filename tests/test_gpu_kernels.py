@@ -48,10 +48,11 @@ def test_gram_float_error_bound(gpu_lib, m, n, kappa):
     assert np.array_equal(w, w.T)
 
 
-def test_gram_empty_rows(gpu_lib):
-    a = gpu_lib.empty_colmajor(0, 5, device="cuda")
+@pytest.mark.parametrize("n", [5, 200, 300])
+def test_gram_empty_rows(gpu_lib, n):
+    a = gpu_lib.empty_colmajor(0, n, device="cuda")
     w = to_host(gpu_lib.gram(a))
-    assert np.array_equal(w, np.zeros((5, 5)))
+    assert np.array_equal(w, np.zeros((n, n)))
 
 
 # -------------------------------------------------------------- CholInv ---
@@ -178,7 +179,9 @@ def test_upper_product_float_bound(gpu_lib):
 
 # ------------------------------------------------- n > 128 (tiled path) ---
 
-@pytest.mark.parametrize("m,n", [(1000, 129), (5003, 200), (20000, 256), (777, 300)])
+@pytest.mark.parametrize("m,n", [(1000, 129), (5003, 200), (20000, 256), (777, 300),
+                                 # n > 256: 128 x 256 tiles, column panels clamped at n, ragged last 16-row chunk
+                                 (300, 300), (16, 257), (5, 300), (1000, 700), (4097, 520)])
 def test_gram_wide_integer_exact(gpu_lib, m, n):
     a = integer_matrix(m, n, 1 << 8, seed=m + n)
     w = to_host(gpu_lib.gram(to_dev(a)))
