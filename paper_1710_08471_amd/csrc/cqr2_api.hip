@@ -438,7 +438,7 @@ int cqr2_gram(const double* A, int64_t m, int64_t n, int64_t lda, double* W, int
     return 0;
   }
   // n > 256: lower triangle by 128 x 128 tiles, then mirrored.
-  CQR2_TRY(cqr2::launch_syrk(cqr2::plan_syrk(m, n), A, m, (int)n, lda, (double*)work, W, ldw, nullptr, s));
+  CQR2_TRY(cqr2::launch_syrk(cqr2::plan_syrk(m, n), 0, A, m, (int)n, lda, (double*)work, W, ldw, nullptr, s));
   CQR2_TRY(cqr2::launch_mirror_lower(W, ldw, n, s));
   return 0;
 }

@@ -256,8 +256,6 @@ hipError_t launch_upper_product_final(const double* X, const double* Y, int64_t 
 // ---- CholeskyQR2 for n > 128 ------------------------------------------------
 GeneralPlan plan_general(int64_t m, int64_t n, bool mixed, int depth) {
   GeneralPlan p{};
-  p.gram_splits = gemm_pick_splits(n, n, m, kPlanCUs);
-  p.apply_splits = 1;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
@@ -273,9 +271,8 @@ GeneralPlan plan_general(int64_t m, int64_t n, bool mixed, int depth) {
   p.off_ri2 = take(nn);
   p.off_p = take(nn);
   p.off_uimg = take(upper_image_bytes(n));
-  size_t gws = gemm_workspace_bytes(n, n, p.gram_splits);
-  if (n <= kWideMaxN) gws = plan_gram_wide(m).partial_bytes;
-  else if (plan_syrk(m, n).partial_bytes > gws) gws = plan_syrk(m, n).partial_bytes;
+  // the Gram's partials (FP64 or FP32 input alike)
+  const size_t gws = n <= kWideMaxN ? plan_gram_wide(m).partial_bytes : plan_syrk(m, n).partial_bytes;
   const size_t rws = cholinv_rec_workspace(n);
   p.off_scratch = take(gws > rws ? gws : rws);
   p.off_q1 = take((size_t)m * n * (mixed ? sizeof(float) : sizeof(double)));
@@ -337,7 +334,7 @@ hipError_t factor_general(const double* A, int64_t m, int64_t n, int64_t lda, do
   if (wide)
     CQR2_HIP(launch_gram_wide(wp, 0, A, m, (int)n, lda, (double*)scratch, W, n, info, s));
   else
-    CQR2_HIP(launch_syrk(sp, A, m, (int)n, lda, (double*)scratch, W, n, info, s));
+    CQR2_HIP(launch_syrk(sp, 0, A, m, (int)n, lda, (double*)scratch, W, n, info, s));
   th.end(0, s);
   if (shifted) CQR2_HIP(launch_shift_diag(W, n, n, m, info, s));
   th.begin(2, s);
@@ -359,11 +356,8 @@ hipError_t factor_general(const double* A, int64_t m, int64_t n, int64_t lda, do
   th.begin(0, s);
   if (wide)
     CQR2_HIP(launch_gram_wide(wp, q1f, Q1, m, (int)n, m, (double*)scratch, W, n, info, s));
-  else if (!mixed)
-    CQR2_HIP(launch_syrk(sp, (const double*)Q1, m, (int)n, m, (double*)scratch, W, n, info, s));
   else
-    CQR2_HIP(launch_gemm_in32(q1f, q1f, 1, 0, n, n, m, 1.0, Q1, m, Q1, m, 0.0, W, n, GEMM_C_LOWER, p.gram_splits,
-                              (double*)scratch, info, s));
+    CQR2_HIP(launch_syrk(sp, q1f, Q1, m, (int)n, m, (double*)scratch, W, n, info, s));
   th.end(0, s);
   th.begin(2, s);
   CQR2_HIP(cholinv_recursive(W, n, n, R2, n, Ri2, n, scratch, info, (int)n, s, depth));
@@ -391,7 +385,7 @@ hipError_t factor_general(const double* A, int64_t m, int64_t n, int64_t lda, do
   if (wide)
     CQR2_HIP(launch_gram_wide(wp, 0, Q, m, (int)n, ldq, (double*)scratch, W, n, info, s));
   else
-    CQR2_HIP(launch_syrk(sp, Q, m, (int)n, ldq, (double*)scratch, W, n, info, s));
+    CQR2_HIP(launch_syrk(sp, 0, Q, m, (int)n, ldq, (double*)scratch, W, n, info, s));
   th.end(0, s);
   th.begin(2, s);
   CQR2_HIP(cholinv_recursive(W, n, n, R1, n, Ri1, n, scratch, info, 2 * (int)n, s));  // R3, R3^-1

@@ -129,8 +129,8 @@ struct SyrkPlan {
   size_t partial_bytes = 0;
 };
 SyrkPlan plan_syrk(int64_t m, int64_t n);
-// Lower triangle of W = AᵀA (FP64 A, any n).
-hipError_t launch_syrk(const SyrkPlan& p, const double* A, int64_t m, int n, int64_t lda, double* partials,
+// Lower triangle of W = AᵀA (any n; A FP64, or FP32 when a_f32, widened exactly).
+hipError_t launch_syrk(const SyrkPlan& p, int a_f32, const void* A, int64_t m, int n, int64_t lda, double* partials,
                        double* W, int64_t ldw, const int32_t* info, hipStream_t s);
 
 // ---- recursive CholInv and the n > 128 driver --------------------------------
@@ -155,7 +155,6 @@ hipError_t launch_upper_product_final(const double* X, const double* Y, int64_t 
 hipError_t launch_mirror_lower(double* W, int64_t ldw, int64_t n, hipStream_t s);
 
 struct GeneralPlan {
-  int gram_splits = 1, apply_splits = 1;
   size_t off_info = 0, off_w = 0, off_r1 = 0, off_ri1 = 0, off_r2 = 0, off_ri2 = 0, off_p = 0, off_uimg = 0,
          off_scratch = 0, off_q1 = 0, off_t = 0;
   size_t total = 0;

@@ -262,14 +262,20 @@ hipError_t launch_gram_wide(const WideGramPlan& p, int a_f32, const void* A, int
 // Blocks and column groups wholly above the diagonal are skipped.  Columns
 // past n are read from column n - 1 (finite data in outputs never written);
 // rows past m are zero.  Partial tiles are summed over the splits in a fixed
-// order by k_syrk_reduce.
+// order by k_syrk_reduce.  An FP32 input (mixed precision's Q1) is staged as
+// FP32 (16 columns per copy, the k slots XOR 4 ((c >> 2) & 3), which keeps
+// the 4-value pieces of the copies whole) and widened exactly when read.
 // ============================================================================
 constexpr int kSyI = 128, kSyJ = 256, kSyK = 16, kSyBufs = 3;
 constexpr int kSyWave = 64 * 64;       // doubles of one wave's partial block
 constexpr int kSyTile = 8 * kSyWave;   // doubles of one workgroup's partial tile
 
-// XOR on the k slots of column c in LDS (even: the 16-byte copies keep their pairs)
-__device__ __forceinline__ int syrk_swz(int c) { return 2 * ((c >> 1) & 7); }
+// XOR on the k slots of column c in LDS (it keeps the values of one 16-byte copy together)
+template <typename TA>
+__device__ __forceinline__ int syrk_swz(int c) {
+  if constexpr (sizeof(TA) == 8) return 2 * ((c >> 1) & 7);
+  else return 4 * ((c >> 2) & 3);
+}
 
 // lower tile t -> (ti, tj): block row ti holds ti / 2 + 1 tiles, so the
 // tiles of block rows 2a and 2a + 1 start at a (a + 1) and (a + 1)^2
@@ -293,11 +299,16 @@ static int syrk_ntiles(int64_t n) {
   return (int)c;
 }
 
-__global__ __launch_bounds__(512, 1) void k_syrk_tile(const double* __restrict__ A, int64_t m, int n, int64_t lda,
+template <typename TA>
+__global__ __launch_bounds__(512, 1) void k_syrk_tile(const TA* __restrict__ A, int64_t m, int n, int64_t lda,
                                                       int64_t chunks_per_split, double* __restrict__ partials,
                                                       int ntiles, const int32_t* __restrict__ info) {
-  constexpr int kIBytes = kSyK * kSyI * 8, kJBytes = kSyK * kSyJ * 8, kBufBytes = kIBytes + kJBytes;
-  constexpr int kPerChunk = 6;  // copies per wave and chunk: 2 of the I panel, 4 of the J panel
+  constexpr int kES = (int)sizeof(TA);
+  constexpr int kIBytes = kSyK * kSyI * kES, kJBytes = kSyK * kSyJ * kES, kBufBytes = kIBytes + kJBytes;
+  // one copy moves 16 bytes per lane: 8 columns of FP64 or 16 of FP32
+  constexpr int kColsPerCopy = 64 * 16 / (kSyK * kES);
+  constexpr int kICopies = kSyI / kColsPerCopy / 8, kJCopies = kSyJ / kColsPerCopy / 8;  // per wave
+  constexpr int kPerChunk = kICopies + kJCopies;
   __shared__ __attribute__((aligned(16))) char smem[kSyBufs * kBufBytes];
   if (info != nullptr && *info != 0) return;
   int ti, tj;
@@ -310,31 +321,35 @@ __global__ __launch_bounds__(512, 1) void k_syrk_tile(const double* __restrict__
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wr = 64 * (wave >> 2), wc = 64 * (wave & 3);
-  const bool aligned = (((uintptr_t)A & 15u) == 0) && ((lda & 1) == 0);
-  auto ibuf = [&](int b) { return (double*)(smem + b * kBufBytes); };
-  auto jbuf = [&](int b) { return (double*)(smem + b * kBufBytes + kIBytes); };
+  const bool aligned = (((uintptr_t)A & 15u) == 0) && (((lda * kES) & 15) == 0);
+  auto ibuf = [&](int b) { return (TA*)(smem + b * kBufBytes); };
+  auto jbuf = [&](int b) { return (TA*)(smem + b * kBufBytes + kIBytes); };
   auto direct_chunk = [&](int p) { return aligned && (cb + p + 1) * kSyK <= m; };
   auto issue = [&](int p) {
     const int b = p % kSyBufs;
     const int64_t row0 = (cb + p) * kSyK;
-    double* Ib = ibuf(b);
-    double* Jb = jbuf(b);
+    TA* Ib = ibuf(b);
+    TA* Jb = jbuf(b);
     if (direct_chunk(p)) {
-      // one copy: 8 columns x 16 rows; lane i -> column 8 t + (i >> 3), k slots 2 (i & 7), +1
-      const int sub = lane >> 3, kp = 2 * (lane & 7);
+      // one copy: kColsPerCopy columns x 16 rows; lane i -> column it kColsPerCopy + i / (64 / kColsPerCopy),
+      // k slots kv (i % (64 / kColsPerCopy)) .. + kv - 1, kv = 16 / kES values
+      constexpr int kLanesPerCol = 64 / kColsPerCopy, kV = 16 / kES;
+      const int sub = lane / kLanesPerCol, kp = kV * (lane % kLanesPerCol);
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        const int it = 2 * wave + t, c = 8 * it + sub;
+      for (int t = 0; t < kICopies; ++t) {
+        const int it = kICopies * wave + t, c = kColsPerCopy * it + sub;
         const int col = I0 + c < n ? I0 + c : n - 1;
-        __builtin_amdgcn_global_load_lds((const void*)(A + row0 + (kp ^ syrk_swz(c)) + (int64_t)col * lda),
-                                         (__attribute__((address_space(3))) void*)(Ib + 8 * it * kSyK), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds((const void*)(A + row0 + (kp ^ syrk_swz<TA>(c)) + (int64_t)col * lda),
+                                         (__attribute__((address_space(3))) void*)(Ib + kColsPerCopy * it * kSyK), 16,
+                                         0, 0);
       }
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int it = 4 * wave + t, c = 8 * it + sub;
+      for (int t = 0; t < kJCopies; ++t) {
+        const int it = kJCopies * wave + t, c = kColsPerCopy * it + sub;
         const int col = J0 + c < n ? J0 + c : n - 1;
-        __builtin_amdgcn_global_load_lds((const void*)(A + row0 + (kp ^ syrk_swz(c)) + (int64_t)col * lda),
-                                         (__attribute__((address_space(3))) void*)(Jb + 8 * it * kSyK), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds((const void*)(A + row0 + (kp ^ syrk_swz<TA>(c)) + (int64_t)col * lda),
+                                         (__attribute__((address_space(3))) void*)(Jb + kColsPerCopy * it * kSyK), 16,
+                                         0, 0);
       }
     } else {
       for (int e = tid; e < kSyK * (kSyI + kSyJ); e += 512) {
@@ -344,7 +359,7 @@ __global__ __launch_bounds__(512, 1) void k_syrk_tile(const double* __restrict__
         int col = (in_i ? I0 : J0) + cc;
         col = col < n ? col : n - 1;
         const int64_t r = row0 + k;
-        (in_i ? Ib : Jb)[cc * kSyK + (k ^ syrk_swz(cc))] = r < m ? A[r + (int64_t)col * lda] : 0.0;
+        (in_i ? Ib : Jb)[cc * kSyK + (k ^ syrk_swz<TA>(cc))] = r < m ? A[r + (int64_t)col * lda] : (TA)0;
       }
     }
   };
@@ -364,8 +379,8 @@ __global__ __launch_bounds__(512, 1) void k_syrk_tile(const double* __restrict__
     else wait_vmcnt<0>();
     lds_barrier();
     if (p + 2 < nch) issue(p + 2);
-    const double* Ib = ibuf(p % kSyBufs);
-    const double* Jb = jbuf(p % kSyBufs);
+    const TA* Ib = ibuf(p % kSyBufs);
+    const TA* Jb = jbuf(p % kSyBufs);
     if (live) {
 #pragma unroll
       for (int ks = 0; ks < kSyK; ks += 4) {
@@ -374,7 +389,7 @@ __global__ __launch_bounds__(512, 1) void k_syrk_tile(const double* __restrict__
 #pragma unroll
         for (int rt = 0; rt < 4; ++rt) {
           const int c = wr + 16 * rt + ar;
-          a[rt] = Ib[c * kSyK + (kk ^ syrk_swz(c))];
+          a[rt] = (double)Ib[c * kSyK + (kk ^ syrk_swz<TA>(c))];
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -383,7 +398,7 @@ __global__ __launch_bounds__(512, 1) void k_syrk_tile(const double* __restrict__
 #pragma unroll
             for (int c4 = 0; c4 < 4; ++c4) {
               const int c = wc + 16 * q + 4 * c4 + bc;
-              b[c4] = Jb[c * kSyK + (kk ^ syrk_swz(c))];
+              b[c4] = (double)Jb[c * kSyK + (kk ^ syrk_swz<TA>(c))];
             }
 #pragma unroll
             for (int c4 = 0; c4 < 4; ++c4)
@@ -443,10 +458,14 @@ SyrkPlan plan_syrk(int64_t m, int64_t n) {
   return p;
 }
 
-hipError_t launch_syrk(const SyrkPlan& p, const double* A, int64_t m, int n, int64_t lda, double* partials,
+hipError_t launch_syrk(const SyrkPlan& p, int a_f32, const void* A, int64_t m, int n, int64_t lda, double* partials,
                        double* W, int64_t ldw, const int32_t* info, hipStream_t s) {
-  hipLaunchKernelGGL(k_syrk_tile, dim3(p.npairs, p.splits), dim3(512), 0, s, A, m, n, lda, p.stages_per_wg, partials,
-                     p.npairs, info);
+  if (a_f32)
+    hipLaunchKernelGGL((k_syrk_tile<float>), dim3(p.npairs, p.splits), dim3(512), 0, s, (const float*)A, m, n, lda,
+                       p.stages_per_wg, partials, p.npairs, info);
+  else
+    hipLaunchKernelGGL((k_syrk_tile<double>), dim3(p.npairs, p.splits), dim3(512), 0, s, (const double*)A, m, n, lda,
+                       p.stages_per_wg, partials, p.npairs, info);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t total = (int64_t)p.npairs * kSyTile;

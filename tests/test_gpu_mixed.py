@@ -35,6 +35,7 @@ def mixed_factor(lib, a):
 @pytest.mark.parametrize("m,n,kappa,seed", [
     (4096, 64, 1e3, 51), (20000, 33, 1e6, 52), (262144 // 8, 256, 1e2, 53), (262144 // 8, 256, 1e4, 54),
     (262144 // 8, 256, 1e6, 55), (262144 // 8, 256, 1e7, 56), (3001, 300, 1e5, 57), (1000, 17, 1e3, 58),
+    (8192, 520, 1e4, 59),  # n > 256 with m % 4 == 0: the FP32 Q1's Gram takes the direct-copy path
 ])
 def test_mixed_gates_against_fp64_oracle(gpu_lib, m, n, kappa, seed):
     a = gdv_matrix(m, n, kappa, seed)
@@ -72,7 +73,7 @@ def hadamard_times_bidiagonal(m, n, seed):
     return hcols, r, hcols @ r
 
 
-@pytest.mark.parametrize("m,n", [(4096, 48), (4096, 200), (16384, 130)])
+@pytest.mark.parametrize("m,n", [(4096, 48), (4096, 200), (16384, 130), (4096, 300)])
 def test_mixed_exact_case_bitwise(gpu_lib, m, n):
     hcols, rr, a = hadamard_times_bidiagonal(m, n, 60 + n)
     q, r, info = mixed_factor(gpu_lib, a)
