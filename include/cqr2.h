@@ -30,6 +30,10 @@
  *    work and Q is unspecified; R is filled with NaN.
  *  - Results are deterministic: the same inputs, sizes and flags give
  *    bit-identical Q and R (fixed reduction orders, no floating-point atomics).
+ *  - Host threads: entry points may be called from several threads at once;
+ *    the library's shared host state (cqr2_factor's cached workspace, the
+ *    timing records, the batched call's task-table ring) is locked.  A server
+ *    handle is not: each cqr2_server is used by one thread at a time.
  */
 #ifndef CQR2_H
 #define CQR2_H
