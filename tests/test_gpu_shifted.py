@@ -10,7 +10,7 @@ import pytest
 import scipy.linalg
 
 import oracle
-from synth import gdv_matrix
+from synth import gdv_matrix, workload_matrix
 from tests.gpu_util import to_dev, to_host
 
 pytestmark = pytest.mark.gpu
@@ -40,6 +40,21 @@ def test_shifted_matches_oracle(gpu_lib, m, n, kappa, seed):
     assert oracle.residual(a, q, r) <= TOL_RES
     assert oracle.rel_fro(r, r_ref) <= TOL_R
     assert np.max(np.abs(r - r_ref)) <= TOL_R * np.linalg.norm(r_ref)
+    assert np.max(np.abs(q - q_ref)) <= TOL_Q
+
+
+@pytest.mark.slow
+def test_shifted_named_1Mx128_workload_full_size(gpu_lib):
+    """The 1048576 x 128 (cond 1e6) problem that `bench.py --shifted` times, in
+    the same launch configuration (factor_ex with the shifted flag)."""
+    a = workload_matrix("tall_1Mx128")
+    q, r, info = shifted_factor(gpu_lib, a)
+    assert info == 0
+    q_ref, r_ref = oracle.scqr3(a)
+    assert np.array_equal(r, np.triu(r)) and np.all(np.diag(r) > 0)
+    assert oracle.orthogonality(q) <= TOL_ORTH
+    assert oracle.residual(a, q, r) <= TOL_RES
+    assert oracle.rel_fro(r, r_ref) <= TOL_R
     assert np.max(np.abs(q - q_ref)) <= TOL_Q
 
 
