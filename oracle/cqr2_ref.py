@@ -25,6 +25,10 @@ itself prescribes.  Readings where the paper is silent:
 * The second pass factors the stored Q1 (in the mixed form: the FP32 values,
   converted exactly to FP64).
 
+Parity unpinned: ``cqr2_mixed``.  The paper fixes no reduced precision, so
+this form has no pin of its own; it is checked against the FP64 oracle, the
+orthogonality invariant and an input on which every FP32 step is exact.
+
 Shifted CholeskyQR3 (``scqr3``): the paper names the shifted variant of
 Fukaya et al. (its Conclusion and the CholeskyQR2 background of its
 Introduction) as an unconditionally stable extension that needs only minimal
