@@ -14,7 +14,12 @@
  *    A, Q, R, work and d_info are DEVICE pointers unless stated otherwise.
  *  - Everything is enqueued on `stream` (a hipStream_t; NULL = legacy default
  *    stream).  Calls return without synchronizing; outputs are valid once the
- *    stream has reached that point.  No host synchronization happens inside.
+ *    stream has reached that point.  No host synchronization happens inside,
+ *    with two exceptions: an entry point that uses the library-cached
+ *    workspace (cqr2_factor; cqr2_cholinv, cqr2_apply_rinv for n > 128;
+ *    cqr2_apply_rinv_f32) synchronizes the device once when that workspace
+ *    has to grow, and the batched call and the server wait for a pinned
+ *    task-table staging buffer when the host runs several calls ahead.
  *  - Ownership: the caller owns A, Q, R, work and d_info.  A is read-only.
  *    Q and R must not overlap A or each other (checked on address ranges).
  *    The library never frees caller memory.
@@ -31,9 +36,14 @@
  *  - Results are deterministic: the same inputs, sizes and flags give
  *    bit-identical Q and R (fixed reduction orders, no floating-point atomics).
  *  - Host threads: entry points may be called from several threads at once;
- *    the library's shared host state (cqr2_factor's cached workspace, the
- *    timing records, the batched call's task-table ring) is locked.  A server
- *    handle is not: each cqr2_server is used by one thread at a time.
+ *    the library's shared host state (the cached workspace, the timing
+ *    records, the batched call's task-table ring) is locked.  The cached
+ *    workspace is ONE device buffer per device, shared by every entry point
+ *    that uses it: a call holds the lock from the lookup until its launches
+ *    are enqueued, so concurrent calls on the same stream are safe, but calls
+ *    on different streams would race on its contents -- they must use the
+ *    entry points that take a work argument.  A server handle is not locked:
+ *    each cqr2_server is used by one thread at a time.
  */
 #ifndef CQR2_H
 #define CQR2_H
@@ -157,8 +167,9 @@ int cqr2_gram(const double* A, int64_t m, int64_t n, int64_t lda,
  * CholeskyQR factors R = Lᵀ and Rinv = Yᵀ = R^{-1} (both n x n upper
  * triangular, column-major, leading dimension ldr; strictly lower parts 0).
  * Reads only the lower triangle of W (n x n, ldw).  d_info (device, may be
- * NULL) receives 0 or the 1-based breakdown column; on breakdown R and Rinv
- * are NaN.
+ * NULL) receives 0 or the 1-based breakdown column; on breakdown the upper
+ * triangles of R and Rinv (diagonal included) are NaN and their strictly lower
+ * parts 0.  For n > 128 it runs on the library-cached workspace.
  */
 int cqr2_cholinv(const double* W, int64_t n, int64_t ldw,
                  double* R, double* Rinv, int64_t ldr, int32_t* d_info, void* stream);
@@ -172,6 +183,20 @@ int cqr2_apply_rinv(const double* A, int64_t m, int64_t n, int64_t lda,
                     const double* U, int64_t ldu, double* Q, int64_t ldq, void* stream);
 
 /*
+ * cqr2_apply_rinv_f32 -- the same product in the mixed-precision form's
+ * arithmetic (pass 1 of CQR2_MIXED_P1_FP32): Q = fl32(A) fl32(U), both
+ * operands rounded to FP32 (nearest even), every product and running sum in
+ * FP32 (FP32 MFMA with FP32 accumulation, k ascending in steps of 4), Q
+ * stored as FP32.  A: m x n FP64 (lda); U: upper triangular n x n FP64 (ldu,
+ * strictly lower part never read); Q: m x n FP32 (ldq >= m, 4-byte aligned),
+ * must not overlap A or U.  Runs on the library-cached workspace (the padded
+ * image of U).  Argument indices: A=1, m=2, n=3, lda=4, U=5, ldu=6, Q=7,
+ * ldq=8.
+ */
+int cqr2_apply_rinv_f32(const double* A, int64_t m, int64_t n, int64_t lda,
+                        const double* U, int64_t ldu, float* Q, int64_t ldq, void* stream);
+
+/*
  * cqr2_upper_product — R = R2 R1 for upper-triangular n x n factors
  * (Algorithm 5, last step).  Column-major, leading dimension ld for all three;
  * R must not overlap R2 or R1.  Strictly lower part of R set to 0.
@@ -180,6 +205,13 @@ int cqr2_upper_product(const double* R2, const double* R1, double* R, int64_t n,
                        int64_t ld, void* stream);
 
 /* ---- many problems at once ------------------------------------------------
+ * The batched call takes a host array of problems and enqueues their task
+ * tables itself; the serving step of the continuous-batching server
+ * (cqr2_server_step) is the one-launch step over every admitted request, with
+ * the task table built and uploaded by the server, so a caller never writes a
+ * device task table.  Each problem's breakdown code goes to its own optional
+ * device word (cqr2_problem.d_info) instead of a separate info array.
+ *
  * One CholeskyQR2 problem (all pointers device, column-major FP64; same rules
  * as cqr2_factor_ex: m >= n >= 0, lda, ldq >= m, ldr >= n, Q and R must not
  * overlap A or each other).  d_info: optional device word receiving the
@@ -236,7 +268,11 @@ int cqr2_factor_batched(const cqr2_problem* probs, int32_t count, void* work, si
  * the host runs more than a few steps ahead (pinned task-table ring).
  * Completion times are HIP event times in milliseconds since the last
  * cqr2_server_clock call.  A, Q and R stay owned by the caller and must stay
- * valid until the request is reported done by cqr2_server_poll.
+ * valid until the request is reported done by cqr2_server_poll.  A (and B) are
+ * read in the order of the server's stream: whatever the caller enqueued on
+ * that stream before the cqr2_server_step call that admits a request is
+ * complete before the request reads its inputs (the large-request streams
+ * wait on an event recorded there).
  */
 typedef struct cqr2_server cqr2_server;
 

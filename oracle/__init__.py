@@ -14,6 +14,7 @@ from .cqr2_ref import (  # noqa: F401
     solve_right_lt,
     cqr2,
     cqr2_mixed,
+    mm_fp32,
     cholesky_shift,
     scqr3,
     lstsq,

@@ -25,9 +25,15 @@ itself prescribes.  Readings where the paper is silent:
 * The second pass factors the stored Q1 (in the mixed form: the FP32 values,
   converted exactly to FP64).
 
-Parity unpinned: ``cqr2_mixed``.  The paper fixes no reduced precision, so
-this form has no pin of its own; it is checked against the FP64 oracle, the
-orthogonality invariant and an input on which every FP32 step is exact.
+Mixed precision (``mm_fp32``, ``cqr2_mixed``): the paper fixes no reduced
+precision.  The reading taken is the one the GPU path offers: pass 1's
+Q1 = A R1^{-1} with both operands rounded to FP32 and every product and
+running sum kept in FP32 (the library's single-precision GEMM), everything
+else FP64.  Its FP32 accumulation is pinned by a designed input whose FP32
+sum is the same in every order yet differs from the correctly rounded exact
+sum, by the standard FP32 summation error bound, and by the fraction of
+entries that differ from the correctly rounded product (an FP64-accumulating
+mistake makes that fraction vanish).
 
 Shifted CholeskyQR3 (``scqr3``): the paper names the shifted variant of
 Fukaya et al. (its Conclusion and the CholeskyQR2 background of its
@@ -80,13 +86,14 @@ def syrk(a: np.ndarray) -> np.ndarray:
 def cholinv(a: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
     """[L, Y] = CholInv(A) (Algorithm 2): A = L Lᵀ with L lower, Y = L^{-1}.
 
-    Steps, for A split into h x h and (n-h) x (n-h) diagonal blocks:
-      base case n == 1: L = sqrt(a), Y = 1 / L;
-      L11, Y11 = CholInv(A11);
-      L21 = A21 Y11ᵀ;
-      L22, Y22 = CholInv(A22 - L21 L21ᵀ);
-      Y21 = -Y22 (L21 Y11)   (the product order of Algorithm 3's last two MMs).
-    Only the lower triangle of ``a`` is read.
+    The recursion halves A.  The leading diagonal block gives its own factor
+    and inverse; the off-diagonal block of L is the leading inverse applied
+    to A's off-diagonal block; the trailing block's factor and inverse come
+    from its Schur complement; and the off-diagonal block of the inverse is
+    minus the trailing inverse times L's off-diagonal block times the leading
+    inverse (multiplied right to left, as Algorithm 3 orders it).  A 1 x 1
+    block is its square root and that root's reciprocal.  Only the lower
+    triangle of ``a`` is read.
     """
     a = np.asarray(a, dtype=np.float64)
     n = a.shape[0]
@@ -164,13 +171,24 @@ def cqr2(a: np.ndarray, return_intermediates: bool = False):
     }
 
 
+def mm_fp32(a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """C = MM(fl32(A), fl32(B)) in FP32 arithmetic, returned as FP32.
+
+    Both operands are rounded to FP32 (round to nearest even); the library's
+    single-precision GEMM then forms every product and every running sum in
+    FP32, in its own summation order.
+    """
+    a32 = np.asarray(a, dtype=np.float64).astype(np.float32)
+    b32 = np.asarray(b, dtype=np.float64).astype(np.float32)
+    return a32 @ b32
+
+
 def cqr2_mixed(a: np.ndarray, return_intermediates: bool = False):
-    """CQR2 with pass 1's Q1 = A R1^{-1} formed in FP32 (FP32 products, FP32 sums).
+    """CQR2 with pass 1's Q1 = A R1^{-1} formed in FP32 (``mm_fp32``).
 
     Gram, CholInv and everything in pass 2 stay FP64; pass 2 factors the stored
     FP32 Q1 after exact conversion to FP64.  Not in the paper (it fixes no
-    precision); it is the reduced-precision variant the GPU path offers, and is
-    checked only against the FP64 oracle and the orthogonality invariant.
+    precision); it is the reduced-precision variant the GPU path offers.
     """
     a = np.asarray(a, dtype=np.float64)
     n = a.shape[1]
@@ -178,7 +196,7 @@ def cqr2_mixed(a: np.ndarray, return_intermediates: bool = False):
     l1, y1 = cholinv(w1)
     r1 = l1.T.copy()
     r1inv = y1.T.copy()
-    q1_32 = a.astype(np.float32) @ r1inv.astype(np.float32)
+    q1_32 = mm_fp32(a, r1inv)
     q1 = q1_32.astype(np.float64)
     try:
         q, r2, r2inv = cqr(q1)

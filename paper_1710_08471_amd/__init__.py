@@ -41,6 +41,7 @@ SIGNATURES = {
     "cqr2_gram": (_i32, [_vp, _i64, _i64, _i64, _vp, _i64, _vp, _sz, _vp]),
     "cqr2_cholinv": (_i32, [_vp, _i64, _i64, _vp, _vp, _i64, _vp, _vp]),
     "cqr2_apply_rinv": (_i32, [_vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp]),
+    "cqr2_apply_rinv_f32": (_i32, [_vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp]),
     "cqr2_upper_product": (_i32, [_vp, _vp, _vp, _i64, _i64, _vp]),
     "cqr2_status_string": (ctypes.c_char_p, [_i32]),
     "cqr2_version": (ctypes.c_char_p, []),
@@ -222,6 +223,22 @@ def apply_rinv(A, U, Q=None):
         Q = empty_colmajor(m, n, device=A.device)
     rc = lib.cqr2_apply_rinv(_ptr(A), m, n, _ld(A), _ptr(U), _ld(U), _ptr(Q), _ld(Q), _stream())
     _check(rc, "cqr2_apply_rinv")
+    return Q
+
+
+def apply_rinv_f32(A, U, Q=None):
+    """Q = fl32(A) fl32(U) in FP32 arithmetic, Q float32 (cqr2_apply_rinv_f32)."""
+    import torch
+    lib = load()
+    _require_cuda_f64(A, "A")
+    _require_cuda_f64(U, "U")
+    m, n = A.shape
+    if Q is None:
+        Q = empty_colmajor(m, n, dtype=torch.float32, device=A.device)
+    if Q.dtype != torch.float32:
+        raise ValueError("Q must be float32")
+    rc = lib.cqr2_apply_rinv_f32(_ptr(A), m, n, _ld(A), _ptr(U), _ld(U), _ptr(Q), _ld(Q), _stream())
+    _check(rc, "cqr2_apply_rinv_f32")
     return Q
 
 

@@ -142,6 +142,12 @@ cqr2::TimerHook timer_hook() {
 }
 
 // ---- library-cached workspace for the entry points without a work argument --
+// One buffer per device, shared by cqr2_factor, cqr2_cholinv (n > 128),
+// cqr2_apply_rinv (n > 128) and cqr2_apply_rinv_f32.  A caller holds the lease
+// (and with it the lock) until its launches are enqueued, so no other thread
+// can replace the buffer between the lookup and the enqueue.  Growing it
+// synchronizes the device before the old buffer is freed, since work enqueued
+// earlier on any stream may still use it.
 struct CachedWs {
   void* ptr = nullptr;
   size_t bytes = 0;
@@ -149,28 +155,34 @@ struct CachedWs {
 std::mutex g_ws_mu;
 std::vector<CachedWs> g_ws;  // per device
 
-void* cached_workspace(size_t bytes, int* err) {
-  std::lock_guard<std::mutex> g(g_ws_mu);
+struct WsLease {
+  std::unique_lock<std::mutex> lock;
+  void* ptr = nullptr;
+  int err = 0;
+};
+
+WsLease cached_workspace(size_t bytes) {
+  WsLease l;
+  l.lock = std::unique_lock<std::mutex>(g_ws_mu);
   int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) { *err = CQR2_ERR_HIP; return nullptr; }
+  if (hipGetDevice(&dev) != hipSuccess) { l.err = CQR2_ERR_HIP; return l; }
   if ((int)g_ws.size() <= dev) g_ws.resize(dev + 1);
   CachedWs& w = g_ws[dev];
   if (bytes == 0) bytes = kAlign;
   if (w.bytes < bytes) {
     if (w.ptr) {
-      // The previous workspace may still be used by enqueued work.
-      if (hipDeviceSynchronize() != hipSuccess) { *err = CQR2_ERR_HIP; return nullptr; }
+      if (hipDeviceSynchronize() != hipSuccess) { l.err = CQR2_ERR_HIP; return l; }
       (void)hipFree(w.ptr);
       w.ptr = nullptr;
       w.bytes = 0;
     }
     void* p = nullptr;
-    if (hipMalloc(&p, bytes) != hipSuccess) { *err = CQR2_ERR_HIP; return nullptr; }
+    if (hipMalloc(&p, bytes) != hipSuccess) { l.err = CQR2_ERR_HIP; return l; }
     w.ptr = p;
     w.bytes = bytes;
   }
-  *err = 0;
-  return w.ptr;
+  l.ptr = w.ptr;
+  return l;
 }
 
 int check_hip(hipError_t e) { return e == hipSuccess ? 0 : CQR2_ERR_HIP; }
@@ -341,10 +353,9 @@ int cqr2_factor(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, d
   const size_t abytes = matrix_bytes(m, n, lda), rbytes = matrix_bytes(n, n, n);
   if (overlaps(A, abytes, Q, abytes)) return -5;
   if (overlaps(A, abytes, R, rbytes) || overlaps(Q, abytes, R, rbytes)) return -6;
-  int err = 0;
-  void* ws = cached_workspace(factor_workspace(m, n, CQR2_FP64), &err);
-  if (err) return err;
-  return run_factor(A, m, n, lda, Q, lda, R, n, (char*)ws, nullptr, CQR2_FP64, (hipStream_t)stream);
+  WsLease ws = cached_workspace(factor_workspace(m, n, CQR2_FP64));
+  if (ws.err) return ws.err;
+  return run_factor(A, m, n, lda, Q, lda, R, n, (char*)ws.ptr, nullptr, CQR2_FP64, (hipStream_t)stream);
 }
 
 size_t cqr2_lstsq_workspace_size(int64_t m, int64_t n, int64_t nrhs) {
@@ -466,15 +477,19 @@ int cqr2_cholinv(const double* W, int64_t n, int64_t ldw, double* R, double* Rin
   // The recursion overwrites the trailing blocks of its input: work on a
   // copy in the library workspace (info word, W copy, recursion scratch).
   const size_t wcopy = align_up((size_t)n * n * sizeof(double));
-  int err = 0;
-  char* ws = (char*)cached_workspace(kAlign + wcopy + cqr2::cholinv_rec_workspace(n), &err);
-  if (err) return err;
+  WsLease lease = cached_workspace(kAlign + wcopy + cqr2::cholinv_rec_workspace(n));
+  if (lease.err) return lease.err;
+  char* ws = (char*)lease.ptr;
   int32_t* info = d_info != nullptr ? d_info : (int32_t*)ws;
   double* Wc = (double*)(ws + kAlign);
   CQR2_TRY(cqr2::launch_set_info(info, 0, s));
   CQR2_TRY(hipMemcpy2DAsync(Wc, n * sizeof(double), W, ldw * sizeof(double), n * sizeof(double), n,
                             hipMemcpyDeviceToDevice, s));
   CQR2_TRY(cqr2::cholinv_recursive(Wc, n, n, R, ldr, Rinv, ldr, ws + kAlign + wcopy, info, 0, s));
+  // after a breakdown the products that follow it skip their work: R and Rinv
+  // become NaN above the diagonal (as the one-workgroup kernel writes them)
+  CQR2_TRY(cqr2::launch_nan_upper_if_info(R, ldr, n, info, s));
+  CQR2_TRY(cqr2::launch_nan_upper_if_info(Rinv, ldr, n, info, s));
   return 0;
 }
 
@@ -505,9 +520,9 @@ int cqr2_apply_rinv(const double* A, int64_t m, int64_t n, int64_t lda, const do
   // in-place product multiplies from a copy of A
   const bool copy_a = in_place && n > cqr2::kWideMaxN;
   const size_t img = align_up(cqr2::upper_image_bytes(n));
-  int err = 0;
-  char* ws = (char*)cached_workspace(img + (copy_a ? (size_t)m * n * sizeof(double) : 0), &err);
-  if (err) return err;
+  WsLease lease = cached_workspace(img + (copy_a ? (size_t)m * n * sizeof(double) : 0));
+  if (lease.err) return lease.err;
+  char* ws = (char*)lease.ptr;
   double* ut = (double*)ws;
   CQR2_TRY(cqr2::launch_upper_image(U, ldu, (int)n, ut, s));
   const double* src = A;
@@ -520,6 +535,31 @@ int cqr2_apply_rinv(const double* A, int64_t m, int64_t n, int64_t lda, const do
     lds = m;
   }
   CQR2_TRY(cqr2::launch_tall_gemm(0, src, m, (int)n, lds, ut, Q, ldq, nullptr, s));
+  return 0;
+}
+
+int cqr2_apply_rinv_f32(const double* A, int64_t m, int64_t n, int64_t lda, const double* U, int64_t ldu,
+                        float* Q, int64_t ldq, void* stream) {
+  if (m < 0) return -2;
+  if (n < 0) return -3;
+  if (lda < (m > 1 ? m : 1)) return -4;
+  if (ldu < (n > 1 ? n : 1)) return -6;
+  if (ldq < (m > 1 ? m : 1)) return -8;
+  if (n == 0 || m == 0) return 0;
+  if (A == nullptr || !aligned8(A)) return -1;
+  if (U == nullptr || !aligned8(U)) return -5;
+  if (Q == nullptr || ((uintptr_t)Q & 3u) != 0) return -7;
+  if (n > CQR2_MAX_N) return CQR2_ERR_UNSUPPORTED;
+  const size_t ab = matrix_bytes(m, n, lda), ub = matrix_bytes(n, n, ldu);
+  const size_t qb = (size_t)((n - 1) * ldq + m) * sizeof(float);
+  if (overlaps(A, ab, Q, qb)) return -7;
+  if (overlaps(U, ub, Q, qb)) return -7;
+  hipStream_t s = (hipStream_t)stream;
+  WsLease lease = cached_workspace(align_up(cqr2::upper_image_bytes(n)));
+  if (lease.err) return lease.err;
+  double* ut = (double*)lease.ptr;
+  CQR2_TRY(cqr2::launch_upper_image(U, ldu, (int)n, ut, s));
+  CQR2_TRY(cqr2::launch_tall_gemm_f32(A, m, (int)n, lda, ut, Q, ldq, nullptr, s));
   return 0;
 }
 

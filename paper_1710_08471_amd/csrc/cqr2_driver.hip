@@ -134,6 +134,22 @@ hipError_t cholinv_recursive(double* W, int64_t ldw, int64_t n, double* R, int64
   return hipSuccess;
 }
 
+// After a breakdown (*info != 0): the upper triangle of X (n x n) := NaN.
+__global__ void k_nan_upper_if_info(double* X, int64_t ldx, int64_t n, const int32_t* info) {
+  if (*info == 0) return;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * n) return;
+  const int64_t i = e % n, j = e / n;
+  if (i <= j) X[i + j * ldx] = __builtin_nan("");
+}
+
+hipError_t launch_nan_upper_if_info(double* X, int64_t ldx, int64_t n, const int32_t* info, hipStream_t s) {
+  const int64_t total = n * n;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_nan_upper_if_info, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, X, ldx, n, info);
+  return hipGetLastError();
+}
+
 __global__ void k_set_info(int32_t* info, int32_t value) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *info = value;
 }

@@ -220,5 +220,7 @@ hipError_t lstsq_tail(const double* Q, int64_t ldq, const double* B, int64_t ldb
 
 // ---- small helpers ---------------------------------------------------------
 hipError_t launch_set_info(int32_t* info, int32_t value, hipStream_t s);
+// X (n x n): upper triangle := NaN if *info != 0 (info must not be null).
+hipError_t launch_nan_upper_if_info(double* X, int64_t ldx, int64_t n, const int32_t* info, hipStream_t s);
 
 }  // namespace cqr2

@@ -211,6 +211,10 @@ struct cqr2_server {
   std::vector<std::pair<int64_t, double>> done;
   std::vector<hipEvent_t> event_pool;
   hipEvent_t t0 = nullptr;
+  // Recorded on `stream` when a large request is admitted; the large stream
+  // waits on it, so the request reads A (and B) only after everything the
+  // caller enqueued on `stream` before the step that admits it.
+  hipEvent_t order_ev = nullptr;
   TableRing ring{8};
   std::vector<char*> dev_tables;      // one device table per ring slot
   int dev_next = 0;
@@ -266,6 +270,8 @@ struct cqr2_server {
         hipStream_t ls = large[large_next];
         large_next = (large_next + 1) % n_large;
         char* ws = arena_base + off;
+        if (hipEventRecord(order_ev, stream) != hipSuccess || hipStreamWaitEvent(ls, order_ev, 0) != hipSuccess)
+          return CQR2_ERR_HIP;
         hipError_t e = cqr2::factor_general(p.A, p.m, p.n, p.lda, p.Q, p.ldq, p.R, p.ldr, ws, plan, false,
                                             p.d_info, ls, cqr2::TimerHook{});
         if (e != hipSuccess) return CQR2_ERR_HIP;
@@ -425,6 +431,7 @@ int cqr2_server_create(size_t arena_bytes, size_t footprint_budget, int32_t max_
     return code;
   };
   if (hipMalloc((void**)&sv->arena_base, arena_bytes) != hipSuccess) return fail(CQR2_ERR_HIP);
+  if (hipEventCreateWithFlags(&sv->order_ev, hipEventDisableTiming) != hipSuccess) return fail(CQR2_ERR_HIP);
   sv->arena.reset(arena_bytes);
   int hw_queues = 4;  // HIP's default hardware queues per process
   if (const char* e = std::getenv("GPU_MAX_HW_QUEUES")) {
@@ -458,6 +465,7 @@ int cqr2_server_destroy(cqr2_server* s) {
   for (auto& f : s->finishing) (void)hipEventDestroy(f.ev);
   for (hipEvent_t e : s->event_pool) (void)hipEventDestroy(e);
   if (s->t0) (void)hipEventDestroy(s->t0);
+  if (s->order_ev) (void)hipEventDestroy(s->order_ev);
   if (s->arena_base) (void)hipFree(s->arena_base);
   delete s;
   return 0;

@@ -116,6 +116,14 @@ def test_step_entry_argument_errors():
     assert lib.cqr2_cholinv(FAKE, 5, 5, FAKE2, FAKE2, 5, NULL, NULL) == -5     # R == Rinv
     assert lib.cqr2_apply_rinv(FAKE, 10, 5, 10, FAKE2, 4, ctypes.c_void_p(0x60000000), 10, NULL) == -6
     assert lib.cqr2_apply_rinv(FAKE, 10, 5, 10, FAKE2, 5, FAKE, 11, NULL) == -8  # in place needs ldq == lda
+    # FP32 product of the mixed form: argument checks only (nothing launched)
+    q32 = ctypes.c_void_p(0x60000000)
+    assert lib.cqr2_apply_rinv_f32(FAKE, 10, 5, 9, FAKE2, 5, q32, 10, NULL) == -4
+    assert lib.cqr2_apply_rinv_f32(FAKE, 10, 5, 10, FAKE2, 4, q32, 10, NULL) == -6
+    assert lib.cqr2_apply_rinv_f32(FAKE, 10, 5, 10, FAKE2, 5, q32, 9, NULL) == -8
+    assert lib.cqr2_apply_rinv_f32(FAKE, 10, 5, 10, FAKE2, 5, ctypes.c_void_p(0x60000002), 10, NULL) == -7
+    assert lib.cqr2_apply_rinv_f32(FAKE, 10, 5, 10, FAKE2, 5, FAKE, 10, NULL) == -7   # Q overlaps A
+    assert lib.cqr2_apply_rinv_f32(FAKE, 10, 0, 10, FAKE2, 1, q32, 10, NULL) == 0     # n == 0: nothing to do
     assert lib.cqr2_upper_product(FAKE, FAKE2, FAKE, 5, 5, NULL) == -3          # R overlaps R2
     assert lib.cqr2_upper_product(FAKE, FAKE2, ctypes.c_void_p(0x60000000), 5, 4, NULL) == -5
 

@@ -112,6 +112,35 @@ def test_server_results_equal_alone(gpu_lib):
         check(a, q, r, MIX[i][2])
 
 
+def test_server_large_request_reads_after_callers_stream(gpu_lib):
+    """A request with n > 128 runs on one of the server's own streams; it must
+    still read A only after the caller's earlier work on the server's stream
+    (here a spin kernel and then the copy that fills A)."""
+    import torch
+    m, n = 20000, 200
+    a = gdv_matrix(m, n, 1e4, 140)
+    src = to_dev(a)
+    A = gpu_lib.empty_colmajor(m, n, device="cuda")
+    A.zero_()
+    Q = gpu_lib.empty_colmajor(m, n, device="cuda")
+    R = gpu_lib.empty_colmajor(n, n, device="cuda")
+    torch.cuda.synchronize()
+    with gpu_lib.Server(256 << 20, 0, 8) as sv:
+        sv.clock()
+        torch.cuda._sleep(20_000_000)     # keeps the stream busy before A is written
+        A.copy_(src)
+        sv.submit(0, A, Q, R)
+        done = []
+        for _ in range(1000):
+            sv.step()
+            done += sv.poll()
+            if done:
+                break
+            torch.cuda.synchronize()
+        assert [t for t, _ in done] == [0]
+    check(a, to_host(Q), to_host(R), 1e4)
+
+
 def test_server_admission_by_footprint(gpu_lib):
     # budget fits about two of these requests: the rest wait in the queue
     mats = [gdv_matrix(20000, 64, 1e3, 120 + i) for i in range(8)]

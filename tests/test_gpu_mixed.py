@@ -13,6 +13,7 @@ import pytest
 
 import oracle
 from synth import gdv_matrix
+from tests import fp32_cases
 from synth.matrices import MIXED_KAPPAS
 from tests.gpu_util import to_dev, to_host
 
@@ -83,6 +84,44 @@ def test_mixed_exact_case_bitwise(gpu_lib, m, n):
     assert np.array_equal(q, hcols / s)
     qf, rf = gpu_lib.factor(to_dev(a))
     assert np.array_equal(to_host(qf), q) and np.array_equal(to_host(rf), r)
+
+
+def test_apply_rinv_f32_designed_case_bitwise(gpu_lib):
+    """Pass 1's FP32 product alone, on the designed input whose FP32 sums are
+    the same in every order and differ from the correctly rounded ones:
+    bitwise equal to the oracle's mm_fp32 wherever the result is order-free."""
+    col = fp32_cases.DESIGNED_COL
+    a, u, rows, signs = fp32_cases.order_free_case()
+    q = to_host(gpu_lib.apply_rinv_f32(to_dev(a), to_dev(u)))
+    ref = oracle.mm_fp32(a, u)
+    assert q.dtype == np.float32
+    assert np.all(q[rows, col] == signs)           # FP32 running sums, not 1 + 2^-23
+    free = np.ones(q.shape, bool)
+    free[:, col] = False
+    free[rows, col] = True
+    assert np.array_equal(q[free], ref[free])
+    # the rest of that column: 4 random terms, order-dependent in FP32
+    ratio, _ = fp32_cases.fp32_sum_stats(q, a, u)
+    assert ratio <= 1.0
+
+
+@pytest.mark.parametrize("m,n,seed", [(2000, 128, 71), (4096, 64, 72), (3001, 256, 73), (1000, 300, 74)])
+def test_apply_rinv_f32_accumulates_in_fp32(gpu_lib, m, n, seed):
+    """On random inputs: within the FP32 summation bound of the exact product,
+    rounded like FP32 running sums (most entries differ from the correctly
+    rounded product), and within twice that bound of the oracle's mm_fp32."""
+    a = gdv_matrix(m, n, 1e6, seed)
+    _, y = oracle.cholinv(oracle.syrk(a))
+    u = y.T.copy()
+    q = to_host(gpu_lib.apply_rinv_f32(to_dev(a), to_dev(u)))
+    ratio, frac = fp32_cases.fp32_sum_stats(q, a, u)
+    assert ratio <= 1.0
+    assert frac >= 0.2
+    ref = oracle.mm_fp32(a, u).astype(np.float64)
+    a32 = a.astype(np.float32).astype(np.float64)
+    u32 = u.astype(np.float32).astype(np.float64)
+    bound = n * U32 * (np.abs(a32) @ np.abs(u32)) + 2.0 ** -149
+    assert np.all(np.abs(q.astype(np.float64) - ref) <= 2 * bound)
 
 
 def test_mixed_breakdown_and_determinism(gpu_lib):

@@ -10,6 +10,10 @@
 * 50-digit Gram-Schmidt (mpmath) on tiny inputs;
 * invariants — A = QR, QᵀQ = I, R upper with positive diagonal, power-of-two
   scaling is exact;
+* FP32 accumulation of the mixed form — a designed sum whose FP32 value is
+  the same in every order but is not the correctly rounded exact sum, the FP32
+  summation error bound, and the share of entries that differ from the
+  correctly rounded product;
 * planted mistakes — mutated copies of the oracle must fail the pins above.
 """
 import json
@@ -22,6 +26,7 @@ import pytest
 import scipy.linalg
 
 import oracle
+from tests import fp32_cases
 from oracle import cqr2_ref
 from synth import gdv_matrix, integer_matrix
 
@@ -220,8 +225,7 @@ def test_cqr2_second_pass_breakdown_offset():
 
 
 def test_mixed_oracle_orthogonality_and_error_level():
-    # Mixed form: not in the paper (parity unpinned by it); pinned to the FP64
-    # oracle and the orthogonality invariant.
+    # Mixed form against the FP64 oracle and the orthogonality invariant.
     a = gdv_matrix(4096, 64, 1e3, 1)
     q, r = oracle.cqr2_mixed(a)
     q64, r64 = oracle.cqr2(a)
@@ -229,6 +233,104 @@ def test_mixed_oracle_orthogonality_and_error_level():
     assert oracle.residual(a, q, r) <= 1e-5       # ~FP32 unit roundoff level
     assert oracle.rel_fro(r, r64) <= 1e-4
     assert oracle.residual(a, q, r) > 1e-12       # really took FP32 arithmetic
+
+
+# --- FP32 accumulation of the mixed form's pass-1 product (mm_fp32) -----------
+
+def _mm_fp64_sums(a, b):
+    """Planted mistake: FP32 operands, but FP64 products and sums, rounded once."""
+    a32 = np.asarray(a, np.float64).astype(np.float32).astype(np.float64)
+    b32 = np.asarray(b, np.float64).astype(np.float32).astype(np.float64)
+    return (a32 @ b32).astype(np.float32)
+
+
+def _mm_fp16_sums(a, b):
+    """Planted mistake: running sums kept in FP16."""
+    a32 = np.asarray(a, np.float64).astype(np.float32)
+    b32 = np.asarray(b, np.float64).astype(np.float32)
+    acc = np.zeros((a32.shape[0], b32.shape[1]), np.float16)
+    for k in range(a32.shape[1]):
+        acc = (acc.astype(np.float32) + np.outer(a32[:, k], b32[k, :])).astype(np.float16)
+    return acc.astype(np.float32)
+
+
+def _mm_dropped_term(a, b):
+    """Planted mistake: the last k term is dropped."""
+    a32 = np.asarray(a, np.float64).astype(np.float32)
+    b32 = np.asarray(b, np.float64).astype(np.float32)
+    return a32[:, :-1] @ b32[:-1, :]
+
+
+def _order_free_pin(mm) -> bool:
+    a, u, rows, signs = fp32_cases.order_free_case()
+    q = np.asarray(mm(a, u))
+    return bool(np.all(q[rows, fp32_cases.DESIGNED_COL] == signs))
+
+
+def _accumulation_pins(mm, a, u) -> bool:
+    ratio, frac = fp32_cases.fp32_sum_stats(mm(a, u), a, u)
+    return ratio <= 1.0 and frac >= 0.2
+
+
+def _random_product_case(seed=5, m=2000, n=128):
+    a = gdv_matrix(m, n, 1e6, seed)
+    _, y = oracle.cholinv(oracle.syrk(a))
+    return a, y.T.copy()
+
+
+def test_designed_fp32_sum_is_order_free_and_not_correctly_rounded():
+    # brute force over every order and pairing of the three FP32 terms
+    for sign in (1.0, -1.0):
+        assert fp32_cases.all_fp32_orders_of_designed_sum(sign) == {sign}
+        assert fp32_cases.exact_fp32_rounding_of_designed_sum(sign) == sign * (1.0 + 2.0 ** -23)
+
+
+def test_mm_fp32_designed_case_exact():
+    a, u, rows, signs = fp32_cases.order_free_case()
+    q = oracle.mm_fp32(a, u)
+    assert q.dtype == np.float32
+    assert np.all(q[rows, fp32_cases.DESIGNED_COL] == signs)
+    # every other entry of these rows is one exact product
+    others = [c for c in range(a.shape[1]) if c != fp32_cases.DESIGNED_COL]
+    assert np.array_equal(q[np.ix_(rows, others)], a[np.ix_(rows, others)].astype(np.float32))
+
+
+def test_mm_fp32_single_products_are_correctly_rounded():
+    # one nonzero per column of U: each entry is one product, rounded once
+    rng = np.random.default_rng(3)
+    a = rng.standard_normal((300, 20))
+    d = 2.0 ** rng.integers(-3, 4, 20)
+    q = oracle.mm_fp32(a, np.diag(d))
+    assert np.array_equal(q, (a.astype(np.float32).astype(np.float64) * d).astype(np.float32))
+
+
+def test_mm_fp32_error_bound_and_fp32_rounding():
+    a, u = _random_product_case()
+    ratio, frac = fp32_cases.fp32_sum_stats(oracle.mm_fp32(a, u), a, u)
+    assert ratio <= 1.0            # within the FP32 summation error bound
+    assert frac >= 0.2             # and rounded like FP32 running sums (measured ~0.9)
+
+
+def test_cqr2_mixed_q1_takes_fp32_sums():
+    a = gdv_matrix(3000, 96, 1e5, 8)
+    _, _, it = oracle.cqr2_mixed(a, return_intermediates=True)
+    assert it["Q1"].dtype == np.float64
+    assert np.array_equal(it["Q1"], it["Q1"].astype(np.float32).astype(np.float64))   # stored FP32 values
+    assert _accumulation_pins(lambda x, y: it["Q1"], a, it["R1inv"])
+
+
+@pytest.mark.parametrize("mutant", [_mm_fp64_sums, _mm_fp16_sums, _mm_dropped_term])
+def test_pins_catch_planted_fp32_accumulation_mistakes(mutant, monkeypatch):
+    assert _order_free_pin(oracle.mm_fp32)
+    a, u = _random_product_case()
+    assert _accumulation_pins(oracle.mm_fp32, a, u)
+    caught = not _order_free_pin(mutant) or not _accumulation_pins(mutant, a, u)
+    assert caught
+    # planted into the oracle itself, the end-to-end Q1 pin fails too
+    monkeypatch.setattr(cqr2_ref, "mm_fp32", mutant)
+    a2 = gdv_matrix(3000, 96, 1e5, 8)
+    _, _, it = cqr2_ref.cqr2_mixed(a2, return_intermediates=True)
+    assert not _accumulation_pins(lambda x, y: it["Q1"].astype(np.float32), a2, it["R1inv"])
 
 
 # ------------------------------------------------------ planted mistakes ---
