@@ -113,6 +113,28 @@ extern "C" {
 int cqr2_factor(const double* A, int64_t m, int64_t n, int64_t lda,
                 double* Q, double* R, void* stream);
 
+/*
+ * cqr2_factor_noalloc — cqr2_factor for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation.  Same arguments, semantics and results (bit for bit) as
+ * cqr2_factor, but it allocates nothing: the workspace is a static device
+ * array of CQR2_NOALLOC_MAX_WORKSPACE bytes per device, part of the library's
+ * code object and held until the process ends.  Every FP64 problem with
+ * n <= 128 fits (any m); larger problems fit while cqr2_workspace_size(m, n,
+ * CQR2_FP64) <= CQR2_NOALLOC_MAX_WORKSPACE, otherwise the call returns
+ * CQR2_ERR_NOALLOC_LIMIT and launches nothing.  The first call with a device
+ * current looks up that device's array address (hipGetSymbolAddress).  All
+ * calls on one device share its array, which keeps the last call's contents
+ * (nothing depends on them): calls that overlap in time on one device -- on
+ * different streams, or from threads using different streams -- race on it and
+ * must be serialized by the caller (for example, one stream).  No timing
+ * records are taken.
+ */
+#define CQR2_NOALLOC_MAX_WORKSPACE ((size_t)18 << 20)
+#define CQR2_ERR_NOALLOC_LIMIT (-103)
+int cqr2_factor_noalloc(const double* A, int64_t m, int64_t n, int64_t lda,
+                        double* Q, double* R, void* stream);
+
 /* Bytes of workspace cqr2_factor_ex needs for (m, n, flags); 0 if unsupported. */
 size_t cqr2_workspace_size(int64_t m, int64_t n, uint32_t flags);
 

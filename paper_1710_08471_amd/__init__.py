@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(_PKG, "libcqr2.so")
 CQR2_ERR_HIP = -100
 CQR2_ERR_UNSUPPORTED = -101
 CQR2_ERR_TOO_LARGE = -102
+CQR2_ERR_NOALLOC_LIMIT = -103
+CQR2_NOALLOC_MAX_WORKSPACE = 18 << 20
 CQR2_FP64 = 0
 CQR2_MIXED_P1_FP32 = 1
 CQR2_SHIFTED_CQR3 = 2
@@ -35,6 +37,7 @@ TIMER_NAMES = ("gram", "gram_reduce", "cholinv", "apply_rinv_pass1", "apply_rinv
 _i64, _u32, _sz, _vp, _i32 = ctypes.c_int64, ctypes.c_uint32, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_int
 SIGNATURES = {
     "cqr2_factor": (_i32, [_vp, _i64, _i64, _i64, _vp, _vp, _vp]),
+    "cqr2_factor_noalloc": (_i32, [_vp, _i64, _i64, _i64, _vp, _vp, _vp]),
     "cqr2_workspace_size": (_sz, [_i64, _i64, _u32]),
     "cqr2_factor_ex": (_i32, [_vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _sz, _vp, _u32, _vp]),
     "cqr2_gram_workspace_size": (_sz, [_i64, _i64]),
@@ -161,6 +164,24 @@ def factor(A):
     R = empty_colmajor(n, n, device=A.device)
     rc = lib.cqr2_factor(_ptr(A), m, n, lda, _ptr(Q), _ptr(R), _stream())
     _check(rc, "cqr2_factor")
+    return Q, R
+
+
+def factor_noalloc(A, Q=None, R=None):
+    """(Q, R) = CholeskyQR2(A) through cqr2_factor_noalloc (the library
+    allocates nothing; Q and R are allocated here when None)."""
+    lib = load()
+    _require_cuda_f64(A, "A")
+    m, n = A.shape
+    lda = _ld(A)
+    if Q is None:
+        Q = empty_colmajor(m, n, device=A.device, ld=lda)
+    if R is None:
+        R = empty_colmajor(n, n, device=A.device)
+    if _ld(Q) != lda or _ld(R) != max(n, 1):
+        raise ValueError("Q must share A's leading dimension and R must have leading dimension n")
+    rc = lib.cqr2_factor_noalloc(_ptr(A), m, n, lda, _ptr(Q), _ptr(R), _stream())
+    _check(rc, "cqr2_factor_noalloc")
     return Q, R
 
 

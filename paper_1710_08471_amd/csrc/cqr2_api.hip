@@ -195,8 +195,8 @@ int check_hip(hipError_t e) { return e == hipSuccess ? 0 : CQR2_ERR_HIP; }
 
 // The enqueued CholeskyQR2 sequence for n <= 128; arguments already validated.
 int run_small(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, int64_t ldq, double* R, int64_t ldr,
-              char* ws, const SmallLayout& L, int32_t* d_info, hipStream_t s, int cus, bool shifted) {
-  const cqr2::TimerHook th = timer_hook();
+              char* ws, const SmallLayout& L, int32_t* d_info, hipStream_t s, int cus, bool shifted,
+              const cqr2::TimerHook& th) {
   int32_t* info = (int32_t*)(ws + L.off_info);
   double* part = (double*)(ws + L.off_part);
   double* W = (double*)(ws + L.off_w);
@@ -244,15 +244,40 @@ int run_small(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, int
 }
 
 int run_factor(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, int64_t ldq, double* R, int64_t ldr,
-               char* ws, int32_t* d_info, uint32_t flags, hipStream_t s) {
+               char* ws, int32_t* d_info, uint32_t flags, hipStream_t s, bool timed = true) {
   const bool shifted = flag_form(flags) == CQR2_SHIFTED_CQR3;
+  const cqr2::TimerHook th = timed ? timer_hook() : cqr2::TimerHook{};
   if (use_small(n, flags))
-    return run_small(A, m, n, lda, Q, ldq, R, ldr, ws, make_small_layout(m, n), d_info, s, device_cus(), shifted);
+    return run_small(A, m, n, lda, Q, ldq, R, ldr, ws, make_small_layout(m, n), d_info, s, device_cus(), shifted, th);
   const bool mixed = flag_form(flags) == CQR2_MIXED_P1_FP32;
   const int depth = flag_depth(flags);
   const cqr2::GeneralPlan p = cqr2::plan_general(m, n, mixed, depth);
-  return check_hip(cqr2::factor_general(A, m, n, lda, Q, ldq, R, ldr, ws, p, mixed, d_info, s, timer_hook(),
-                                        shifted, depth));
+  return check_hip(cqr2::factor_general(A, m, n, lda, Q, ldq, R, ldr, ws, p, mixed, d_info, s, th, shifted, depth));
+}
+
+// ---- static scratch of the no-allocation entry point -------------------------
+// One array per device (each device holds its own copy of the code object's
+// globals), kept until the process ends.  Host code never uses the array's
+// name as an address: the device address is looked up once per device and
+// kept in g_scratch_ptr.
+static __device__ __align__(256) char scratch[CQR2_NOALLOC_MAX_WORKSPACE];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call made with that device current).
+int scratch_address(void** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return CQR2_ERR_HIP;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) return CQR2_ERR_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return 0;
 }
 
 }  // namespace
@@ -281,6 +306,7 @@ const char* cqr2_status_string(int code) {
     case CQR2_ERR_HIP: return "HIP runtime error";
     case CQR2_ERR_UNSUPPORTED: return "unsupported problem size";
     case CQR2_ERR_TOO_LARGE: return "request can never fit the server's arena or footprint budget";
+    case CQR2_ERR_NOALLOC_LIMIT: return "problem needs more workspace than the no-allocation scratch holds";
     default: break;
   }
   if (code < 0 && code > -20) return "invalid argument (see the argument index = -code)";
@@ -356,6 +382,26 @@ int cqr2_factor(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, d
   WsLease ws = cached_workspace(factor_workspace(m, n, CQR2_FP64));
   if (ws.err) return ws.err;
   return run_factor(A, m, n, lda, Q, lda, R, n, (char*)ws.ptr, nullptr, CQR2_FP64, (hipStream_t)stream);
+}
+
+int cqr2_factor_noalloc(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, double* R, void* stream) {
+  if (n < 0) return -3;
+  if (m < n) return -2;
+  if (lda < (m > 1 ? m : 1)) return -4;
+  if (n == 0) return 0;
+  if (A == nullptr || !aligned8(A)) return -1;
+  if (Q == nullptr || !aligned8(Q)) return -5;
+  if (R == nullptr || !aligned8(R)) return -6;
+  if (n > CQR2_MAX_N) return CQR2_ERR_UNSUPPORTED;
+  const size_t abytes = matrix_bytes(m, n, lda), rbytes = matrix_bytes(n, n, n);
+  if (overlaps(A, abytes, Q, abytes)) return -5;
+  if (overlaps(A, abytes, R, rbytes) || overlaps(Q, abytes, R, rbytes)) return -6;
+  if (factor_workspace(m, n, CQR2_FP64) > CQR2_NOALLOC_MAX_WORKSPACE) return CQR2_ERR_NOALLOC_LIMIT;
+  void* ws = nullptr;
+  if (const int rc = scratch_address(&ws)) return rc;
+  // the first Gram launch clears the info word; every other workspace block
+  // is written before it is read, so the previous call's contents never leak
+  return run_factor(A, m, n, lda, Q, lda, R, n, (char*)ws, nullptr, CQR2_FP64, (hipStream_t)stream, false);
 }
 
 size_t cqr2_lstsq_workspace_size(int64_t m, int64_t n, int64_t nrhs) {

@@ -62,6 +62,23 @@ def test_factor_argument_errors():
     assert f(NULL, 10, 0, 10, NULL, NULL, NULL) == 0                # n == 0: quick return
 
 
+def test_factor_noalloc_argument_errors():
+    # host checks only: nothing reaches the GPU
+    lib = cq.load()
+    assert lib.cqr2_factor_noalloc(FAKE, 10, 5, 9, FAKE2, ctypes.c_void_p(0x60000000), NULL) == -4
+    assert lib.cqr2_factor_noalloc(FAKE, 4, 5, 10, FAKE2, ctypes.c_void_p(0x60000000), NULL) == -2
+    assert lib.cqr2_factor_noalloc(NULL, 10, 5, 10, FAKE2, ctypes.c_void_p(0x60000000), NULL) == -1
+    assert lib.cqr2_factor_noalloc(FAKE, 10, 5, 10, FAKE, ctypes.c_void_p(0x60000000), NULL) == -5
+    assert lib.cqr2_factor_noalloc(FAKE, 10, 0, 10, NULL, NULL, NULL) == 0
+    # every n <= 128 problem fits the static scratch; a bigger workspace is refused
+    limit = cq.CQR2_NOALLOC_MAX_WORKSPACE
+    assert max(lib.cqr2_workspace_size(m, 128, 0) for m in (128, 4096, 1 << 20, 1 << 30)) <= limit
+    assert lib.cqr2_workspace_size(1 << 20, 200, 0) > limit
+    assert lib.cqr2_factor_noalloc(ctypes.c_void_p(1 << 40), 1 << 20, 200, 1 << 20, ctypes.c_void_p(1 << 41),
+                                   ctypes.c_void_p(1 << 42), NULL) == cq.CQR2_ERR_NOALLOC_LIMIT
+    assert "no-allocation" in lib.cqr2_status_string(cq.CQR2_ERR_NOALLOC_LIMIT).decode()
+
+
 def test_factor_ex_argument_errors():
     lib = cq.load()
     f = lib.cqr2_factor_ex
