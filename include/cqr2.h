@@ -130,7 +130,7 @@ int cqr2_factor(const double* A, int64_t m, int64_t n, int64_t lda,
  * must be serialized by the caller (for example, one stream).  No timing
  * records are taken.
  */
-#define CQR2_NOALLOC_MAX_WORKSPACE ((size_t)18 << 20)
+#define CQR2_NOALLOC_MAX_WORKSPACE ((size_t)20 << 20)
 #define CQR2_ERR_NOALLOC_LIMIT (-103)
 int cqr2_factor_noalloc(const double* A, int64_t m, int64_t n, int64_t lda,
                         double* Q, double* R, void* stream);

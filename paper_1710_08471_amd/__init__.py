@@ -20,7 +20,7 @@ CQR2_ERR_HIP = -100
 CQR2_ERR_UNSUPPORTED = -101
 CQR2_ERR_TOO_LARGE = -102
 CQR2_ERR_NOALLOC_LIMIT = -103
-CQR2_NOALLOC_MAX_WORKSPACE = 18 << 20
+CQR2_NOALLOC_MAX_WORKSPACE = 20 << 20
 CQR2_FP64 = 0
 CQR2_MIXED_P1_FP32 = 1
 CQR2_SHIFTED_CQR3 = 2

@@ -19,7 +19,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libcqr2.so")
 OBJDIR = os.path.join(ROOT, "_build")
-SOURCES = ["cqr2_gram.hip", "cqr2_cholinv.hip", "cqr2_apply.hip", "cqr2_gemm.hip", "cqr2_wide.hip", "cqr2_driver.hip",
+SOURCES = ["cqr2_gram.hip", "cqr2_cholinv.hip", "cqr2_apply.hip", "cqr2_gemm.hip", "cqr2_wide.hip", "cqr2_stream16.hip", "cqr2_driver.hip",
            "cqr2_step.hip", "cqr2_serve.hip", "cqr2_api.hip"]
 ARCH = "gfx950"
 FLAGS = [

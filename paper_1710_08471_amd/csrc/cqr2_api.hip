@@ -45,9 +45,13 @@ int device_cus() {
   return cus;
 }
 
-// Workspace layout of one factorization with n <= 128.
+// Workspace layout of one factorization with n <= 128.  For 64 < n <= 128
+// (padded order 128) the MFMA 16x16x4 streaming kernels run (s16), with pass
+// 2's Gram fused into pass 1's Q = A R1^-1.
 struct SmallLayout {
   GramPlan gram;
+  cqr2::Stream16Plan s16p;
+  bool s16 = false;
   int np = 0;
   size_t off_info = 0, off_part = 0, off_w = 0, off_u1 = 0, off_u2 = 0, off_r1 = 0, off_r2 = 0;
   size_t total = 0;
@@ -57,9 +61,11 @@ SmallLayout make_small_layout(int64_t m, int64_t n) {
   SmallLayout L;
   L.gram = cqr2::plan_gram(m, n);
   L.np = cqr2::padded_order(n);
+  L.s16 = L.np == 128;
+  if (L.s16) L.s16p = cqr2::plan_stream16(m);
   size_t off = 0;
   L.off_info = off; off += align_up(sizeof(int32_t) * 4);
-  L.off_part = off; off += align_up(L.gram.partial_bytes);
+  L.off_part = off; off += align_up(L.s16 ? L.s16p.partial_bytes : L.gram.partial_bytes);
   L.off_w = off;    off += align_up((size_t)n * n * sizeof(double));
   L.off_u1 = off;   off += align_up((size_t)L.np * L.np * sizeof(double));
   L.off_u2 = off;   off += align_up((size_t)L.np * L.np * sizeof(double));
@@ -205,13 +211,49 @@ int run_small(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, int
   double* R1 = (double*)(ws + L.off_r1);
   double* R2 = (double*)(ws + L.off_r2);
   const int ni = (int)n;
+  auto reduce = [&]() -> hipError_t {
+    return L.s16 ? cqr2::launch_stream16_reduce(L.s16p, part, ni, W, n, info, s)
+                 : cqr2::launch_gram_reduce(L.gram, part, ni, W, n, info, s);
+  };
   auto cholinv = [&](double* Rk, double* Uk, int info_offset) -> int {
-    th.begin(1, s); CQR2_TRY(cqr2::launch_gram_reduce(L.gram, part, ni, W, n, info, s)); th.end(1, s);
+    th.begin(1, s); CQR2_TRY(reduce()); th.end(1, s);
     if (shifted && info_offset == 0) CQR2_TRY(cqr2::launch_shift_diag(W, n, n, m, info, s));
     th.begin(2, s); CQR2_TRY(cqr2::launch_cholinv(W, n, ni, Rk, n, nullptr, 0, Uk, L.np, info, info_offset, s));
     th.end(2, s);
     return 0;
   };
+  constexpr int kUp = cqr2::GEMM_A_UPPER | cqr2::GEMM_B_UPPER | cqr2::GEMM_C_UPPER;
+  if (L.s16) {
+    // ---- pass 1: Gram of A (clears the info word), CholInv; Q1 = A U1 with
+    //      the Gram of the stored Q1 (pass 2's first step) in the same launch ----
+    th.begin(0, s); CQR2_TRY(cqr2::launch_stream16_gram(L.s16p, A, m, ni, lda, part, nullptr, s, info)); th.end(0, s);
+    if (const int rc = cholinv(R1, U1, 0)) return rc;
+    th.begin(3, s);
+    CQR2_TRY(cqr2::launch_stream16_apply_gram(L.s16p, A, m, ni, lda, U1, Q, ldq, part, info, s));
+    th.end(3, s);
+    // ---- pass 2: CholInv of Q1's Gram, Q = Q1 U2 in place ----
+    if (const int rc = cholinv(R2, U2, ni)) return rc;
+    if (!shifted) {
+      th.begin(4, s); CQR2_TRY(cqr2::launch_stream16_apply(L.s16p, Q, m, ni, ldq, U2, Q, ldq, info, s)); th.end(4, s);
+      th.begin(5, s);
+      CQR2_TRY(cqr2::launch_upper_product_final(R2, R1, n, R, ldr, info, d_info, s));
+      th.end(5, s);
+      return 0;
+    }
+    // ---- shifted CholeskyQR3: pass 2's Q with the Gram of the third pass ----
+    th.begin(4, s);
+    CQR2_TRY(cqr2::launch_stream16_apply_gram(L.s16p, Q, m, ni, ldq, U2, Q, ldq, part, info, s));
+    th.end(4, s);
+    CQR2_TRY(cqr2::launch_gemm(0, 0, n, n, n, 1.0, R2, n, R1, n, 0.0, R, ldr, kUp, 1, nullptr, info, s));
+    th.begin(1, s); CQR2_TRY(reduce()); th.end(1, s);
+    th.begin(2, s); CQR2_TRY(cqr2::launch_cholinv(W, n, ni, R2, n, nullptr, 0, U1, L.np, info, 2 * ni, s)); th.end(2, s);
+    th.begin(4, s); CQR2_TRY(cqr2::launch_stream16_apply(L.s16p, Q, m, ni, ldq, U1, Q, ldq, info, s)); th.end(4, s);
+    th.begin(5, s);
+    CQR2_TRY(cqr2::launch_gemm(0, 0, n, n, n, 1.0, R2, n, R, ldr, 0.0, W, n, kUp, 1, nullptr, info, s));
+    CQR2_TRY(cqr2::launch_finalize_r(W, n, R, ldr, n, info, d_info, s));
+    th.end(5, s);
+    return 0;
+  }
   // ---- pass 1: CQR(A); the first Gram clears the info word ----
   th.begin(0, s);
   CQR2_TRY(cqr2::launch_gram_partials(L.gram, A, m, ni, lda, part, nullptr, s, info));
@@ -222,7 +264,6 @@ int run_small(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, int
   th.begin(0, s); CQR2_TRY(cqr2::launch_gram_partials(L.gram, Q, m, ni, ldq, part, info, s)); th.end(0, s);
   if (const int rc = cholinv(R2, U2, ni)) return rc;
   th.begin(4, s); CQR2_TRY(cqr2::launch_apply_rinv(Q, m, ni, ldq, U2, L.np, 1, Q, ldq, info, cus, s)); th.end(4, s);
-  constexpr int kUp = cqr2::GEMM_A_UPPER | cqr2::GEMM_B_UPPER | cqr2::GEMM_C_UPPER;
   if (!shifted) {
     // ---- R = R2 R1 ----
     th.begin(5, s);
@@ -233,7 +274,7 @@ int run_small(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, int
   // ---- shifted CholeskyQR3: R2 R1 held in the caller's R, a third pass on Q ----
   CQR2_TRY(cqr2::launch_gemm(0, 0, n, n, n, 1.0, R2, n, R1, n, 0.0, R, ldr, kUp, 1, nullptr, info, s));
   th.begin(0, s); CQR2_TRY(cqr2::launch_gram_partials(L.gram, Q, m, ni, ldq, part, info, s)); th.end(0, s);
-  th.begin(1, s); CQR2_TRY(cqr2::launch_gram_reduce(L.gram, part, ni, W, n, info, s)); th.end(1, s);
+  th.begin(1, s); CQR2_TRY(reduce()); th.end(1, s);
   th.begin(2, s); CQR2_TRY(cqr2::launch_cholinv(W, n, ni, R2, n, nullptr, 0, U1, L.np, info, 2 * ni, s)); th.end(2, s);
   th.begin(4, s); CQR2_TRY(cqr2::launch_apply_rinv(Q, m, ni, ldq, U1, L.np, 1, Q, ldq, info, cus, s)); th.end(4, s);
   th.begin(5, s);

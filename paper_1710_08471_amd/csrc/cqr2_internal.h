@@ -1,6 +1,6 @@
 // Internal launch interface between the C ABI (cqr2_api.hip, cqr2_serve.hip)
 // and the kernels (cqr2_gram.hip, cqr2_cholinv.hip, cqr2_apply.hip,
-// cqr2_gemm.hip, cqr2_wide.hip, cqr2_step.hip, cqr2_driver.hip).
+// cqr2_gemm.hip, cqr2_wide.hip, cqr2_stream16.hip, cqr2_step.hip, cqr2_driver.hip).
 // Not installed; no torch types anywhere.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -64,6 +64,30 @@ hipError_t launch_cholinv(const double* W, int64_t ldw, int n, double* R, int64_
 // is read).  Q may alias A exactly (in place).
 hipError_t launch_apply_rinv(const double* A, int64_t m, int n, int64_t lda, const double* U, int64_t urs,
                              int64_t ucs, double* Q, int64_t ldq, const int32_t* info, int num_cus, hipStream_t s);
+
+// ---- 64 < n <= 128 on MFMA 16x16x4 (cqr2_stream16.hip) ----------------------
+// Row stages split over up to 256 workgroups; partial Grams are 36 lower
+// 16 x 16 tiles per workgroup.  U: the padded 128 x 128 row-major image of
+// R^{-1} that launch_cholinv writes (np = 128).
+struct Stream16Plan {
+  int64_t stages = 0, stages_per_wg = 0;
+  int splits = 0;
+  size_t partial_bytes = 0;
+};
+Stream16Plan plan_stream16(int64_t m);
+// Partial Grams of A; reset_info as launch_gram_partials.
+hipError_t launch_stream16_gram(const Stream16Plan& p, const double* A, int64_t m, int n, int64_t lda,
+                                double* partials, const int32_t* info, hipStream_t s, int32_t* reset_info = nullptr);
+// Q = A U; Q may equal A (in place, ldq == lda).
+hipError_t launch_stream16_apply(const Stream16Plan& p, const double* A, int64_t m, int n, int64_t lda,
+                                 const double* Upad, double* Q, int64_t ldq, const int32_t* info, hipStream_t s);
+// Q = A U and the partial Grams of the stored Q; Q may equal A.
+hipError_t launch_stream16_apply_gram(const Stream16Plan& p, const double* A, int64_t m, int n, int64_t lda,
+                                      const double* Upad, double* Q, int64_t ldq, double* partials,
+                                      const int32_t* info, hipStream_t s);
+// Fixed-order sum of the partials into the symmetric W (n x n, ldw).
+hipError_t launch_stream16_reduce(const Stream16Plan& p, const double* partials, int n, double* W, int64_t ldw,
+                                  const int32_t* info, hipStream_t s);
 
 // ---- general FP64 GEMM: C = alpha op(A) op(B) + beta C ----------------------
 // Triangle flags are semantic: entries outside a declared triangle of A or B
