@@ -41,9 +41,19 @@ def flops_householder(m: int, n: int) -> float:
 
 
 # Timer classes of the library (cqr2_timing_read order) grouped by the kernel
-# they time on the n <= 128 FP64 path.
-KERNEL_CLASSES = {
-    "k_apply_rinv": ("apply_rinv_pass1", "apply_rinv_pass2"),
+# they time, per path.  64 < n <= 128: the MFMA 16x16x4 streaming kernels,
+# pass 2's Gram fused into pass 1's Q1 (k_fused16).  n <= 64: the MFMA 4x4x4
+# kernels, two Grams and two Q products.
+KERNEL_CLASSES_S16 = {
+    "k_fused16": ("q_pass1",),
+    "k_apply16": ("q_pass2",),
+    "k_gram16": ("gram",),
+    "k_gram16_reduce": ("gram_reduce",),
+    "k_cholinv": ("cholinv",),
+    "k_upper_product_final": ("upper_product",),
+}
+KERNEL_CLASSES_SMALL = {
+    "k_apply_rinv": ("q_pass1", "q_pass2"),
     "k_gram_partials": ("gram",),
     "k_gram_reduce": ("gram_reduce",),
     "k_cholinv": ("cholinv",),
@@ -51,26 +61,30 @@ KERNEL_CLASSES = {
 }
 
 
-def kernel_units(kernel: str, m: int, n: int, mixed: bool = False):
-    """Algorithmic work of ONE launch of `kernel` at (m, n): (bound, flops, bytes).
+def kernel_units(kernel: str, m: int, n: int):
+    """Algorithmic work of ONE launch of `kernel` at (m, n): (flops, bytes).
 
     Flops count multiply-adds of the triangle actually needed (2 per product);
     bytes are the minimum HBM traffic: each operand read once, each output
     written once.
     """
     tri = m * n * (n + 1)            # 2 flops x (n (n+1) / 2 products per row)
-    if kernel == "k_gram_partials":
-        return "mfma", float(tri), 8.0 * m * n                  # reads A once
-    if kernel == "k_apply_rinv":
-        return "hbm", float(tri), 16.0 * m * n                  # reads A, writes Q
+    if kernel in ("k_gram_partials", "k_gram16"):
+        return float(tri), 8.0 * m * n                  # reads A once
+    if kernel in ("k_apply_rinv", "k_apply16"):
+        return float(tri), 16.0 * m * n                 # reads A, writes Q
+    if kernel == "k_fused16":
+        return 2.0 * tri, 16.0 * m * n                  # Q1 = A U1 and the Gram of Q1: reads A, writes Q1
+    if kernel == "k_gram16_reduce":
+        return 0.0, 8.0 * 256 * 36 * 256                # partial Grams read once
     if kernel == "k_gram_reduce":
         ng = 1
         while ng < (n + 3) // 4:
             ng *= 2
-        return "hbm", 0.0, 8.0 * 256 * 16 * (ng * (ng + 1) // 2)  # partial Grams read once
+        return 0.0, 8.0 * 256 * 16 * (ng * (ng + 1) // 2)
     if kernel == "k_cholinv":
-        return "alu", 2.0 * n ** 3 / 3.0, 8.0 * n * n
-    return "alu", 2.0 * n ** 3 / 3.0, 24.0 * n * n
+        return 2.0 * n ** 3 / 3.0, 8.0 * n * n
+    return 2.0 * n ** 3 / 3.0, 24.0 * n * n
 
 
 def read_traffic(kernel: str):
@@ -380,13 +394,17 @@ def main():
     }
 
     # Dominant kernel (largest total time over the K instrumented steps) and its
-    # roofline; only the n <= 128 FP64 path has one kernel per timer class.
+    # roofline; only the n <= 128 FP64 path has one kernel per timer class.  The
+    # bound is the roof the kernel's algorithmic work meets first: HBM bytes
+    # at 8 TB/s against FP64 flops at 78.6 TF/s.
     if n <= 128 and not args.mixed and not args.shifted:
-        tot = {k: sum(kt[c][0] for c in cls if kt.get(c, (0, 0))[1]) for k, cls in KERNEL_CLASSES.items()}
-        cnt = {k: sum(kt[c][1] for c in cls if kt.get(c, (0, 0))[1]) for k, cls in KERNEL_CLASSES.items()}
+        classes = KERNEL_CLASSES_S16 if n > 64 else KERNEL_CLASSES_SMALL
+        tot = {k: sum(kt[c][0] for c in cls if kt.get(c, (0, 0))[1]) for k, cls in classes.items()}
+        cnt = {k: sum(kt[c][1] for c in cls if kt.get(c, (0, 0))[1]) for k, cls in classes.items()}
         dom = max(tot, key=tot.get)
         avg_ms = tot[dom] / cnt[dom]
-        bound, fl, by = kernel_units(dom, m, n)
+        fl, by = kernel_units(dom, m, n)
+        bound = "hbm" if by / (HBM_PEAK_GBS * 1e9) >= fl / (FP64_PEAK_TFLOPS * 1e12) else "mfma"
         if bound == "hbm":
             achieved = by / (avg_ms / 1e3) / 1e9
             roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

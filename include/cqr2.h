@@ -341,8 +341,10 @@ const char* cqr2_version(void);
  * When enabled, cqr2_factor/_ex record a HIP event pair around each kernel
  * they launch (on the call's stream).  cqr2_timing_read synchronizes on the
  * recorded events and returns, per kernel class, the total milliseconds and
- * launch count since the last reset.  Classes: 0 gram, 1 gram-reduce,
- * 2 cholinv, 3 apply-rinv (pass 1), 4 apply-rinv (pass 2), 5 upper-product.
+ * launch count since the last reset.  Classes: 0 Gram, 1 Gram reduction,
+ * 2 CholInv, 3 pass 1's Q1 = A R1^{-1} (for 64 < n <= 128 the same launch also
+ * forms pass 2's partial Grams), 4 pass 2's Q = Q1 R2^{-1} (and the shifted
+ * form's later passes), 5 R = R2 R1 with the finalization.
  */
 #define CQR2_NUM_TIMERS 6
 int cqr2_timing_enable(int enable);

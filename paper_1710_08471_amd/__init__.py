@@ -31,7 +31,7 @@ def CQR2_INVERSE_DEPTH(d: int) -> int:
     """Flag bits of the partial inverse with depth d (OR onto CQR2_FP64)."""
     return int(d) << 8
 NUM_TIMERS = 6
-TIMER_NAMES = ("gram", "gram_reduce", "cholinv", "apply_rinv_pass1", "apply_rinv_pass2", "upper_product")
+TIMER_NAMES = ("gram", "gram_reduce", "cholinv", "q_pass1", "q_pass2", "upper_product")
 
 # Every symbol include/cqr2.h declares, with (restype, argtypes).
 _i64, _u32, _sz, _vp, _i32 = ctypes.c_int64, ctypes.c_uint32, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_int

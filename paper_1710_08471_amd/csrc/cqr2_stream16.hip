@@ -48,9 +48,6 @@ constexpr int kSplits = 256;                    // workgroups along m for large 
 // dword 3 of a raw buffer resource on gfx9-family parts (32-bit data format,
 // no swizzle): loads within num_records bytes of the base
 constexpr int kBufferRsrcWord3 = 0x00020000;
-#ifndef CQR2_S16_KSPLIT
-#define CQR2_S16_KSPLIT 0
-#endif
 
 // stage rows and ring depth per kernel (measured at 1M x 128)
 constexpr int kGramSR = 64, kGramNBUF = 2;
@@ -224,11 +221,9 @@ __device__ __forceinline__ void wave_body(const double* A, int64_t m, int n, int
     const int lr = ln & 15, lk = ln >> 4;
 
     if constexpr (kApply) {
-      // accumulators per row tile and column tile, split by the parity of the
-      // k-step (two independent chains each), added at the end
-      d4 acc[kRTW][2], acc2[kRTW][2];
+      d4 acc[kRTW][2];
 #pragma unroll
-      for (int a = 0; a < kRTW; ++a) acc[a][0] = acc[a][1] = acc2[a][0] = acc2[a][1] = d4{0.0, 0.0, 0.0, 0.0};
+      for (int a = 0; a < kRTW; ++a) acc[a][0] = acc[a][1] = d4{0.0, 0.0, 0.0, 0.0};
       // A fragment of row tile rt, k-step t: lane l holds A(16 rt + l%16, 4t + l/16);
       // the next k-step's fragments are read while this one multiplies
       auto afrag = [&](int t, int q) { return buf[spos<SR>(4 * t + lk, 16 * (R::HALF * kRTW + q) + lr)]; };
@@ -245,8 +240,8 @@ __device__ __forceinline__ void wave_body(const double* A, int64_t m, int n, int
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int q = 0; q < kRTW; ++q) {
-          d4& c1 = (CQR2_S16_KSPLIT && (t & 1)) ? acc2[q][1] : acc[q][1];
-          d4& c0 = (CQR2_S16_KSPLIT && (t & 1)) ? acc2[q][0] : acc[q][0];
+          d4& c1 = acc[q][1];
+          d4& c0 = acc[q][0];
           if constexpr (MODE == MODE_APPLY) {
             // Qᵀ = Uᵀ Aᵀ: entry r of lane l is Q(16 rt + l%16, 16 J + 4r + l/16)
             c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(u1[t], a[t & 1][q], c1, 0, 0, 0);
@@ -258,13 +253,6 @@ __device__ __forceinline__ void wave_body(const double* A, int64_t m, int n, int
           }
         }
         __builtin_amdgcn_sched_barrier(0);
-      }
-      if constexpr (CQR2_S16_KSPLIT) {
-#pragma unroll
-        for (int q = 0; q < kRTW; ++q) {
-          acc[q][0] += acc2[q][0];
-          acc[q][1] += acc2[q][1];
-        }
       }
       if constexpr (MODE == MODE_APPLY) {
         // coalesced stores: per entry r, 4 columns x 16 consecutive rows
@@ -380,33 +368,61 @@ __device__ __forceinline__ void wave_body(const double* A, int64_t m, int n, int
 
 // ---- Q1 = A U with the Gram of the stored Q1, producer / consumer -----------
 // Waves 0..3 (one per SIMD) form Q1 stage i from A stage i (column tiles P and
-// 7 - P, both 16-row tiles of an SR = 32 stage) and write it to an LDS tile;
-// waves 4..7 accumulate the Gram of Q1 stage i - 1 from the other LDS tile
-// (SIMD s: the lower tile rows 7 - s and s, nine tiles) and store that stage to
-// global memory.  One barrier per stage; every SIMD gets 72 products of each
-// kind per stage, interleaved by its two waves.
-template <int W>
-struct FusedGram {
-  static constexpr int S = W - 4;
-  static constexpr int GA = kTiles - 1 - S, GB = S;  // tile rows
-  static constexpr int N = (GA + 1) + (GB + 1);      // 9
-  static constexpr int NF = GA + 1;                  // column tiles 0 .. GA (GB <= GA)
-  static constexpr int tile_i(int k) { return k <= GA ? GA : GB; }
-  static constexpr int tile_j(int k) { return k <= GA ? k : k - (GA + 1); }
+// 7 - P, both 16-row tiles of an SR = 32 stage, taken as its even and odd
+// rows) and write it to an LDS tile; the other waves accumulate the Gram of Q1
+// stage i - 1 from the other LDS tile and store that stage to global memory.
+// One barrier per stage.  With NWF = 8 waves, Gram wave 4 + s owns the nine
+// lower tiles of rows 7 - s and s (SIMD s); with NWF = 12, those nine tiles go
+// to two waves of SIMD s, five and four (GramTiles).  Every SIMD gets 72
+// products of each kind per stage.
+template <int NWF, int W>
+struct FusedTiles {
+  struct List {
+    int I[9], J[9], fi[9], fj[9];
+    int F[8];
+    int n, nf;
+  };
+  static constexpr List make() {
+    List l{};
+    int pos[kTiles] = {-1, -1, -1, -1, -1, -1, -1, -1};
+    auto add = [&](int I, int J) {
+      if (pos[I] < 0) { pos[I] = l.nf; l.F[l.nf++] = I; }
+      if (pos[J] < 0) { pos[J] = l.nf; l.F[l.nf++] = J; }
+      l.I[l.n] = I; l.J[l.n] = J; l.fi[l.n] = pos[I]; l.fj[l.n] = pos[J];
+      ++l.n;
+    };
+    if (W < 4) return l;
+    if (NWF == 8) {
+      const int S = W - 4, GA = kTiles - 1 - S, GB = S;
+      for (int j = 0; j <= GA; ++j) add(GA, j);
+      for (int j = 0; j <= GB; ++j) add(GB, j);
+    } else {
+      const int g = W - 4, S = g & 3, first = g < 4 ? 0 : 5, cnt = g < 4 ? 5 : 4;
+      for (int k = first; k < first + cnt; ++k) {
+        const int I = k < kTiles - S ? kTiles - 1 - S : S, J = k < kTiles - S ? k : k - (kTiles - S);
+        add(I, J);
+      }
+    }
+    return l;
+  }
+  static constexpr List list = make();
+  static constexpr int N = list.n > 0 ? list.n : 1;
+  static constexpr int NF = list.nf > 0 ? list.nf : 1;
 };
 
-template <int SR, int NBUF, int W>
+template <int SR, int NBUF, int NWF, int W>
 __device__ __forceinline__ void fused_body(const double* A, int64_t m, int n, int64_t lda,
                                            const double* __restrict__ U, double* Q, int64_t ldq,
                                            double* __restrict__ out, int64_t s_begin, int64_t s_end, bool desc,
                                            bool direct_ok, bool qvec_ok, double* smem) {
   constexpr int kBuf = kCols * SR;
-  constexpr int kRT = SR / 16;              // 16-row tiles per stage (all of them per apply wave)
   constexpr int kLPC = SR / 2;
   constexpr int kCPI = 64 / kLPC;
   constexpr int kInstr = kCols / kCPI;
+  constexpr int kThr = 64 * NWF;
+  constexpr int kGW = NWF - 4;              // Gram waves
   constexpr bool kApplyWave = W < 4;
-  static_assert(kInstr % kWaves == 0 && kInstr % 4 == 0, "stage shape");
+  static_assert(SR == 32, "the apply waves take a 32-row stage as two interleaved row tiles");
   double* qbuf = smem + NBUF * kBuf;        // two Q1 tiles
 
   const int tid = threadIdx.x, lane = tid & 63;
@@ -424,20 +440,19 @@ __device__ __forceinline__ void fused_body(const double* A, int64_t m, int n, in
 #pragma unroll
     for (int t = 0; t < K1; ++t) u1[t] = U[(4 * t + lk) * kCols + 16 * J1 + lr];
   }
-  using G = FusedGram<(kApplyWave ? 4 : W)>;
+  using G = FusedTiles<NWF, W>;
   d4 gacc[G::N];
 #pragma unroll
   for (int k = 0; k < G::N; ++k) gacc[k] = d4{0.0, 0.0, 0.0, 0.0};
 
   int fcount = 0;
-#pragma unroll
-  for (int p = W; p < kInstr; p += kWaves) fcount += (kCPI * p < n) ? 1 : 0;
+  for (int p = W; p < kInstr; p += NWF) fcount += (kCPI * p < n) ? 1 : 0;
   auto fill = [&](int64_t st, double* buf) {
     const int64_t row0 = st * SR;
     if (direct_ok && row0 + SR <= m) {
       const int sub = lane / kLPC, lrow = 2 * (lane % kLPC);
 #pragma unroll
-      for (int p = W; p < kInstr; p += kWaves) {
+      for (int p = W; p < kInstr; p += NWF) {
         if (kCPI * p < n) {
           const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
               (void*)(A + row0 + (int64_t)(kCPI * p) * lda), 0, 0x7fffffff, kBufferRsrcWord3);
@@ -451,7 +466,7 @@ __device__ __forceinline__ void fused_body(const double* A, int64_t m, int n, in
         }
       }
     } else {
-      for (int e = tid; e < kBuf; e += kThreads) {
+      for (int e = tid; e < kBuf; e += kThr) {
         const int c = e / SR, r = e % SR;
         const int64_t row = row0 + r;
         if (c < n) buf[spos<SR>(c, r)] = row < m ? A[row + (int64_t)c * lda] : 0.0;
@@ -478,25 +493,26 @@ __device__ __forceinline__ void fused_body(const double* A, int64_t m, int n, in
       if (i < count) {
         const double* buf = smem + (int)(i % NBUF) * kBuf;
         double* qb = qbuf + (int)(i & 1) * kBuf;
-        static_assert(SR == 32, "the apply waves take a 32-row stage as two interleaved row tiles");
         // row tile q = 0 holds the stage's even rows, q = 1 its odd rows: one
-        // 16-byte read gives lane l A(2 (l%16), 4t + l/16) and the row below
+        // 16-byte read gives lane l A(2 (l%16), 4t + l/16) and the row below;
+        // the reads run two k-steps ahead of the products
         d4 acc[2][2];
 #pragma unroll
         for (int q = 0; q < 2; ++q) acc[q][0] = acc[q][1] = d4{0.0, 0.0, 0.0, 0.0};
         auto afrag = [&](int t) { return *reinterpret_cast<const double2*>(buf + spos<SR>(4 * t + lk, 2 * lr)); };
-        double2 a[2];
+        double2 a[3];
         a[0] = afrag(0);
+        a[1] = afrag(1);
 #pragma unroll
         for (int t = 0; t < K1; ++t) {
-          if (t + 1 < K1) a[(t + 1) & 1] = afrag(t + 1);
+          if (t + 2 < K1) a[(t + 2) % 3] = afrag(t + 2);
           __builtin_amdgcn_sched_barrier(0);
           // Q = A U: entry r of lane l is Q(row 4r + l/16 of the tile, 16 J + l%16)
-          acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t & 1].x, u1[t], acc[0][1], 0, 0, 0);
-          acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t & 1].y, u1[t], acc[1][1], 0, 0, 0);
+          acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t % 3].x, u1[t], acc[0][1], 0, 0, 0);
+          acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t % 3].y, u1[t], acc[1][1], 0, 0, 0);
           if (t < K0) {
-            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t & 1].x, u0[t], acc[0][0], 0, 0, 0);
-            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t & 1].y, u0[t], acc[1][0], 0, 0, 0);
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t % 3].x, u0[t], acc[0][0], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t % 3].y, u0[t], acc[1][0], 0, 0, 0);
           }
           __builtin_amdgcn_sched_barrier(0);
         }
@@ -513,11 +529,11 @@ __device__ __forceinline__ void fused_body(const double* A, int64_t m, int n, in
     } else {
       if (i >= 1) {
         const double* qb = qbuf + (int)((i - 1) & 1) * kBuf;
-        // Gram of Q1 stage i - 1: one 16-byte read per column tile c and row
+        // Gram of Q1 stage i - 1: one 16-byte read per column tile and row
         // block t of 8 rows gives lane l Q1(8t + 2 (l/16), 16 c + l%16) and the
         // row below (two k-steps); tile (I, J) += Q1_Iᵀ Q1_J
         auto gfrag = [&](int t, int c) {
-          return *reinterpret_cast<const double2*>(qb + spos<SR>(16 * c + lr, 8 * t + 2 * lk));
+          return *reinterpret_cast<const double2*>(qb + spos<SR>(16 * G::list.F[c] + lr, 8 * t + 2 * lk));
         };
         double2 f[2][G::NF];
 #pragma unroll
@@ -531,11 +547,11 @@ __device__ __forceinline__ void fused_body(const double* A, int64_t m, int n, in
           __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
           for (int k = 0; k < G::N; ++k)
-            gacc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(f[t & 1][G::tile_i(k)].x, f[t & 1][G::tile_j(k)].x,
+            gacc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(f[t & 1][G::list.fi[k]].x, f[t & 1][G::list.fj[k]].x,
                                                            gacc[k], 0, 0, 0);
 #pragma unroll
           for (int k = 0; k < G::N; ++k)
-            gacc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(f[t & 1][G::tile_i(k)].y, f[t & 1][G::tile_j(k)].y,
+            gacc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(f[t & 1][G::list.fi[k]].y, f[t & 1][G::list.fj[k]].y,
                                                            gacc[k], 0, 0, 0);
           __builtin_amdgcn_sched_barrier(0);
         }
@@ -543,7 +559,7 @@ __device__ __forceinline__ void fused_body(const double* A, int64_t m, int n, in
         const int64_t row0 = stage_at(i - 1) * SR;
         const int sub = lane / kLPC, lrow = 2 * (lane % kLPC);
 #pragma unroll
-        for (int p = W - 4; p < kInstr; p += 4) {
+        for (int p = W - 4; p < kInstr; p += kGW) {
           if (kCPI * p < n) {
             const int col = kCPI * p + sub;
             const int grow = lrow ^ ((col & 15) << 1);
@@ -571,7 +587,7 @@ __device__ __forceinline__ void fused_body(const double* A, int64_t m, int n, in
   if constexpr (!kApplyWave) {
 #pragma unroll
     for (int k = 0; k < G::N; ++k) {
-      const int I = G::tile_i(k), J = G::tile_j(k);
+      const int I = G::list.I[k], J = G::list.J[k];
       double* o = out + (int64_t)(I * (I + 1) / 2 + J) * 256;
 #pragma unroll
       for (int r = 0; r < 4; ++r) o[r * 64 + lane] = gacc[k][r];
@@ -579,15 +595,57 @@ __device__ __forceinline__ void fused_body(const double* A, int64_t m, int n, in
   }
 }
 
+constexpr int kFusedWaves = 12;  // four Q1 waves, eight Gram waves (three per SIMD)
+
+// The fused kernel (see fused_body); partial Grams as k_stream16.
+template <int SR, int NBUF, int NWF>
+__device__ __forceinline__ void fused16_kernel(const double* A, int64_t m, int n, int64_t lda,
+                                               const double* __restrict__ U, double* Q, int64_t ldq,
+                                               double* __restrict__ partials, int64_t stages, int64_t spw, int desc,
+                                               const int32_t* info) {
+  __shared__ __attribute__((aligned(16))) double smem[(NBUF + 2) * kCols * SR];
+  if (info != nullptr && *info != 0) return;
+  constexpr int kF = kPlanRows / SR;
+  const int64_t nst = (m + SR - 1) / SR;
+  const int64_t u0 = (int64_t)blockIdx.x * spw;
+  const int64_t u1 = u0 + spw < stages ? u0 + spw : stages;
+  const int64_t s0 = u0 * kF;
+  const int64_t s1 = u1 * kF < nst ? u1 * kF : nst;
+  for (int e = threadIdx.x; e < (NBUF + 2) * kCols * SR; e += 64 * NWF)
+    if ((e % (kCols * SR)) / SR >= n) smem[e] = 0.0;
+  const bool direct_ok = (((uintptr_t)A & 15u) == 0) && ((lda & 1) == 0) && lda <= ((int64_t)1 << 26);
+  const bool qvec_ok = (((uintptr_t)Q & 15u) == 0) && ((ldq & 1) == 0);
+  double* out = partials + (int64_t)blockIdx.x * kLower * 256;
+  const bool d = desc != 0;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+#define CQR2_F16(WV) fused_body<SR, NBUF, NWF, WV>(A, m, n, lda, U, Q, ldq, out, s0, s1, d, direct_ok, qvec_ok, smem)
+  switch (wave) {
+    case 0: CQR2_F16(0); break;
+    case 1: CQR2_F16(1); break;
+    case 2: CQR2_F16(2); break;
+    case 3: CQR2_F16(3); break;
+    case 4: CQR2_F16(4); break;
+    case 5: CQR2_F16(5); break;
+    case 6: CQR2_F16(6); break;
+    case 7: CQR2_F16(7); break;
+    case 8: if constexpr (NWF > 8) CQR2_F16(8); break;
+    case 9: if constexpr (NWF > 9) CQR2_F16(9); break;
+    case 10: if constexpr (NWF > 10) CQR2_F16(10); break;
+    case 11: if constexpr (NWF > 11) CQR2_F16(11); break;
+    default: break;
+  }
+#undef CQR2_F16
+}
+
 // Each workgroup walks its range of SR-row stages (descending if desc);
 // partial Grams of the workgroup at partials + blockIdx.x * 36 * 256.  reset_info: the first kernel
 // of a factorization clears the info word (workgroup 0) and reads none.
 template <int MODE, int SR, int NBUF>
-__global__ __launch_bounds__(kThreads, 1) void k_stream16(const double* A, int64_t m, int n, int64_t lda,
-                                                         const double* __restrict__ U, double* Q, int64_t ldq,
-                                                         double* __restrict__ partials, int64_t stages,
-                                                         int64_t spw, int desc, int32_t* info, int reset_info) {
-  __shared__ __attribute__((aligned(16))) double smem[(NBUF + (MODE == MODE_APPLY_GRAM ? 2 : 0)) * kCols * SR];
+__device__ __forceinline__ void stream16_kernel(const double* A, int64_t m, int n, int64_t lda,
+                                                const double* __restrict__ U, double* Q, int64_t ldq,
+                                                double* __restrict__ partials, int64_t stages, int64_t spw, int desc,
+                                                int32_t* info, int reset_info) {
+  __shared__ __attribute__((aligned(16))) double smem[NBUF * kCols * SR];
   if (reset_info) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *info = 0;
   } else if (info != nullptr && *info != 0) {
@@ -601,7 +659,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_stream16(const double* A, int64
   const int64_t s0 = u0 * kF;
   const int64_t s1 = u1 * kF < nst ? u1 * kF : nst;
   // columns >= n are never copied: zero them in every buffer once
-  for (int e = threadIdx.x; e < (NBUF + (MODE == MODE_APPLY_GRAM ? 2 : 0)) * kCols * SR; e += kThreads)
+  for (int e = threadIdx.x; e < NBUF * kCols * SR; e += kThreads)
     if ((e % (kCols * SR)) / SR >= n) smem[e] = 0.0;
   // direct copies: 16-byte row pairs, and a column pair's byte offset within
   // the 32-bit buffer offset
@@ -610,11 +668,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_stream16(const double* A, int64
   double* out = partials != nullptr ? partials + (int64_t)blockIdx.x * kLower * 256 : nullptr;
   const bool d = desc != 0;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-#define CQR2_S16(WV)                                                                          \
-  if constexpr (MODE == MODE_APPLY_GRAM)                                                      \
-    fused_body<SR, NBUF, WV>(A, m, n, lda, U, Q, ldq, out, s0, s1, d, direct_ok, qvec_ok, smem); \
-  else                                                                                        \
-    wave_body<MODE, SR, NBUF, WV>(A, m, n, lda, U, Q, ldq, out, s0, s1, d, direct_ok, qvec_ok, smem)
+#define CQR2_S16(WV) wave_body<MODE, SR, NBUF, WV>(A, m, n, lda, U, Q, ldq, out, s0, s1, d, direct_ok, qvec_ok, smem)
   switch (wave) {
     case 0: CQR2_S16(0); break;
     case 1: CQR2_S16(1); break;
@@ -632,7 +686,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_stream16(const double* A, int64
 // Sum of the partials in split order (8 contiguous sub-ranges added in
 // order, then the 8 sums in order); writes the lower triangle of W and its
 // mirror.
-__global__ __launch_bounds__(256) void k_stream16_reduce(const double* __restrict__ part, int splits, int n,
+__device__ __forceinline__ void stream16_reduce(const double* __restrict__ part, int splits, int n,
                                                          double* __restrict__ W, int64_t ldw,
                                                          const int32_t* __restrict__ info) {
   __shared__ double red[8][32];
@@ -673,6 +727,35 @@ __global__ __launch_bounds__(256) void k_stream16_reduce(const double* __restric
 
 }  // namespace
 
+// The named kernels (one name per role, for traces and counters).
+template <int SR, int NBUF>
+__global__ __launch_bounds__(kThreads, 1) void k_gram16(const double* A, int64_t m, int n, int64_t lda,
+                                                       double* __restrict__ partials, int64_t stages, int64_t spw,
+                                                       int32_t* info, int reset_info) {
+  stream16_kernel<MODE_GRAM, SR, NBUF>(A, m, n, lda, nullptr, nullptr, 0, partials, stages, spw, 0, info, reset_info);
+}
+
+template <int SR, int NBUF>
+__global__ __launch_bounds__(kThreads, 1) void k_apply16(const double* A, int64_t m, int n, int64_t lda,
+                                                        const double* __restrict__ U, double* Q, int64_t ldq,
+                                                        int64_t stages, int64_t spw, int32_t* info) {
+  stream16_kernel<MODE_APPLY, SR, NBUF>(A, m, n, lda, U, Q, ldq, nullptr, stages, spw, 0, info, 0);
+}
+
+template <int SR, int NBUF, int NWF>
+__global__ __launch_bounds__(64 * NWF, 1) void k_fused16(const double* A, int64_t m, int n, int64_t lda,
+                                                        const double* __restrict__ U, double* Q, int64_t ldq,
+                                                        double* __restrict__ partials, int64_t stages, int64_t spw,
+                                                        const int32_t* info) {
+  fused16_kernel<SR, NBUF, NWF>(A, m, n, lda, U, Q, ldq, partials, stages, spw, 1, info);
+}
+
+__global__ __launch_bounds__(256) void k_gram16_reduce(const double* __restrict__ part, int splits, int n,
+                                                       double* __restrict__ W, int64_t ldw,
+                                                       const int32_t* __restrict__ info) {
+  stream16_reduce(part, splits, n, W, ldw, info);
+}
+
 Stream16Plan plan_stream16(int64_t m) {
   Stream16Plan p{};
   p.stages = m > 0 ? (m + kPlanRows - 1) / kPlanRows : 1;
@@ -687,32 +770,31 @@ Stream16Plan plan_stream16(int64_t m) {
 
 hipError_t launch_stream16_gram(const Stream16Plan& p, const double* A, int64_t m, int n, int64_t lda,
                                 double* partials, const int32_t* info, hipStream_t s, int32_t* reset_info) {
-  hipLaunchKernelGGL((k_stream16<MODE_GRAM, kGramSR, kGramNBUF>), dim3(p.splits), dim3(kThreads), 0, s, A, m, n, lda,
-                     (const double*)nullptr, (double*)nullptr, (int64_t)0, partials, p.stages, p.stages_per_wg, 0,
-                     reset_info != nullptr ? reset_info : const_cast<int32_t*>(info), reset_info != nullptr ? 1 : 0);
+  hipLaunchKernelGGL((k_gram16<kGramSR, kGramNBUF>), dim3(p.splits), dim3(kThreads), 0, s, A, m, n, lda, partials,
+                     p.stages, p.stages_per_wg, reset_info != nullptr ? reset_info : const_cast<int32_t*>(info),
+                     reset_info != nullptr ? 1 : 0);
   return hipGetLastError();
 }
 
 hipError_t launch_stream16_apply(const Stream16Plan& p, const double* A, int64_t m, int n, int64_t lda,
                                  const double* Upad, double* Q, int64_t ldq, const int32_t* info, hipStream_t s) {
-  hipLaunchKernelGGL((k_stream16<MODE_APPLY, kApplySR, kApplyNBUF>), dim3(p.splits), dim3(kThreads), 0, s, A, m, n, lda, Upad,
-                     Q, ldq, (double*)nullptr, p.stages, p.stages_per_wg, 0, const_cast<int32_t*>(info), 0);
+  hipLaunchKernelGGL((k_apply16<kApplySR, kApplyNBUF>), dim3(p.splits), dim3(kThreads), 0, s, A, m, n, lda, Upad, Q,
+                     ldq, p.stages, p.stages_per_wg, const_cast<int32_t*>(info));
   return hipGetLastError();
 }
 
 hipError_t launch_stream16_apply_gram(const Stream16Plan& p, const double* A, int64_t m, int n, int64_t lda,
                                       const double* Upad, double* Q, int64_t ldq, double* partials,
                                       const int32_t* info, hipStream_t s) {
-  hipLaunchKernelGGL((k_stream16<MODE_APPLY_GRAM, kFusedSR, kFusedNBUF>), dim3(p.splits), dim3(kThreads), 0, s, A, m, n, lda,
-                     Upad, Q, ldq, partials, p.stages, p.stages_per_wg, 1, const_cast<int32_t*>(info), 0);
+  hipLaunchKernelGGL((k_fused16<kFusedSR, kFusedNBUF, kFusedWaves>), dim3(p.splits), dim3(64 * kFusedWaves), 0, s, A,
+                     m, n, lda, Upad, Q, ldq, partials, p.stages, p.stages_per_wg, info);
   return hipGetLastError();
 }
 
 hipError_t launch_stream16_reduce(const Stream16Plan& p, const double* partials, int n, double* W, int64_t ldw,
                                   const int32_t* info, hipStream_t s) {
   constexpr int total = kLower * 256;
-  hipLaunchKernelGGL(k_stream16_reduce, dim3((total + 31) / 32), dim3(256), 0, s, partials, p.splits, n, W, ldw,
-                     info);
+  hipLaunchKernelGGL(k_gram16_reduce, dim3((total + 31) / 32), dim3(256), 0, s, partials, p.splits, n, W, ldw, info);
   return hipGetLastError();
 }
 

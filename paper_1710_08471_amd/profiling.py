@@ -51,6 +51,10 @@ KERNEL_SOURCE = {
     "k_tall": ["cqr2_wide.hip", "sync_dev.h"],
     "k_upper_image": ["cqr2_wide.hip", "sync_dev.h"],
     "k_step": ["cqr2_step.hip", "gram_dev.h", "cholinv_dev.h", "apply_dev.h"],
+    "k_gram16": ["cqr2_stream16.hip", "sync_dev.h"],
+    "k_apply16": ["cqr2_stream16.hip", "sync_dev.h"],
+    "k_fused16": ["cqr2_stream16.hip", "sync_dev.h"],
+    "k_gram16_reduce": ["cqr2_stream16.hip", "sync_dev.h"],
 }
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
