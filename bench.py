@@ -144,13 +144,35 @@ SERVE_BUDGET = 64 << 30        # in-flight footprint budget (A, Q, R, workspace)
 SERVE_SLOTS = 256
 
 
+def device_checks(torch, a, q, r, x=None, b=None):
+    """Invariants of a served result, computed on the device in FP64 (the
+    comparison with the CPU oracle is the GPU tests' job): orthogonality,
+    residual, R upper triangular with a positive diagonal, and for a
+    least-squares request the optimality of X (Aᵀ(AX - B) = 0, relative)."""
+    n = q.shape[1]
+    qt = q.t().contiguous()
+    eye = torch.eye(n, dtype=torch.float64, device=q.device)
+    orth = float(torch.linalg.norm(qt @ q - eye))
+    resid = float(torch.linalg.norm(a - q @ r) / torch.linalg.norm(a))
+    upper = bool(torch.equal(r, torch.triu(r))) and bool((torch.diagonal(r) > 0).all())
+    out = {"orthogonality": orth, "residual": resid,
+           "ok": bool(orth <= 1e-12 and resid <= 1e-13 and upper)}
+    if x is not None:
+        at = a.t().contiguous()
+        g = at @ (a @ x - b)
+        scale = float(torch.linalg.norm(at @ a) * torch.linalg.norm(x) + torch.linalg.norm(at @ b))
+        opt = float(torch.linalg.norm(g)) / scale
+        out["normal_eq_rel"] = opt
+        out["ok"] = bool(out["ok"] and opt <= 1e-12)
+    return out
+
+
 def serve_stream(cq, torch, count: int, rate: float, seed: int):
     """Closed-loop capacity and open-loop latency of the continuous-batching
-    server on the request mix; a sample of results is checked against the
-    CPU oracle on the same input bytes."""
+    server on the request mix; a sample of results is checked on the device
+    (device_checks)."""
     import numpy as np
 
-    import oracle
     from synth import gdv_matrix_device, request_mix
 
     reqs = request_mix(count, rate, seed)
@@ -211,35 +233,82 @@ def serve_stream(cq, torch, count: int, rate: float, seed: int):
     mixed["lstsq_requests"] = len(lsq)
     log(f"serving open loop at {rate:.0f}/s, 1 in 4 requests least squares: {mixed}")
 
-    # oracle check on the first request of every n in the mix (the last run
-    # served the least-squares requests: their X is checked too)
+    # device-side checks on the first request of every n in the mix (the last
+    # run served the least-squares requests: their X is checked too)
     checked = []
     for nn in sorted({r.n for r in reqs}):
         k = next(r.idx for r in reqs if r.n == nn)
-        a = mats[k].cpu().numpy()
-        q, r_ = qs[k].cpu().numpy(), rs[k].cpu().numpy()
-        q_ref, r_ref = oracle.cqr2(a)
-        ok = (oracle.orthogonality(q) <= 1e-12 and oracle.residual(a, q, r_) <= 1e-13
-              and oracle.rel_fro(r_, r_ref) <= 1e-9)
-        checked.append({"request": k, "m": reqs[k].m, "n": nn, "ok": bool(ok)})
+        c = device_checks(torch, mats[k], qs[k], rs[k])
+        checked.append({"request": k, "m": reqs[k].m, "n": nn, **c})
     for nn in sorted({r.n for r in reqs}):
         k = next((r.idx for r in reqs if r.n == nn and r.idx in lsq), None)
         if k is None:
             continue
-        a = mats[k].cpu().numpy()
-        b = lsq[k][0].cpu().numpy()
-        x_ref, _, _ = oracle.lstsq(a, b)
-        x = lsq[k][1].cpu().numpy()
-        ok = np.linalg.norm(x - x_ref) <= 1e-12 * max(reqs[k].kappa, 10.0) * np.linalg.norm(x_ref)
-        checked.append({"request": k, "m": reqs[k].m, "n": nn, "lstsq_nrhs": b.shape[1], "ok": bool(ok)})
+        c = device_checks(torch, mats[k], qs[k], rs[k], x=lsq[k][1], b=lsq[k][0])
+        checked.append({"request": k, "m": reqs[k].m, "n": nn, "lstsq_nrhs": int(lsq[k][0].shape[1]), **c})
     return {
         "requests": count, "rate_per_s": rate, "seed": seed,
         "mix": "m log-uniform [1024,131072], n in {16,32,64,128,256}, kappa log-uniform [1e1,1e6]",
         "solves_per_s": opened["solves_per_s"], "p50_ms": opened["p50_ms"], "p99_ms": opened["p99_ms"],
         "closed_loop": closed, "open_loop": opened, "open_loop_0.8C": high, "open_loop_lstsq_mix": mixed,
-        "oracle_sample": checked,
+        "device_check_sample": checked,
         "slots": SERVE_SLOTS, "arena_bytes": SERVE_ARENA, "footprint_budget": SERVE_BUDGET,
     }
+
+
+def mixed_sweep(cq, torch, steps: int, warmup: int):
+    """The 262144 x 256 comparison problem (A = G D V, generated on the device)
+    at each condition number of the sweep: CholeskyQR2 in plain FP64 and with pass 1's Q1 in FP32
+    (CQR2_MIXED_P1_FP32), each timed over `steps` calls; orthogonality and
+    residual of both, and the mixed R against the FP64 R (both on the device)."""
+    from synth import WORKLOADS, gdv_matrix_device
+    from synth.matrices import MIXED_KAPPAS
+
+    wl = WORKLOADS["mixed_262144x256"]
+    m, n = wl.m, wl.n
+    lib = cq.load()
+    dev = torch.device("cuda:0")
+    sp = cq.ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    wbytes = max(lib.cqr2_workspace_size(m, n, f) for f in (cq.CQR2_FP64, cq.CQR2_MIXED_P1_FP32))
+    work = torch.empty(wbytes, dtype=torch.uint8, device=dev)
+    rows = []
+    for kappa in sorted(MIXED_KAPPAS):
+        # generated on the device (same recipe, torch's seeded generator): the
+        # two forms factor the same bytes
+        a = gdv_matrix_device(m, n, kappa, MIXED_KAPPAS[kappa], device=dev)
+        res = {}
+        for name, flags in (("fp64", cq.CQR2_FP64), ("mixed", cq.CQR2_MIXED_P1_FP32)):
+            q = cq.empty_colmajor(m, n, device=dev)
+            r = cq.empty_colmajor(n, n, device=dev)
+
+            def step():
+                rc = lib.cqr2_factor_ex(cq._ptr(a), m, n, m, cq._ptr(q), m, cq._ptr(r), n, cq._ptr(work), wbytes,
+                                        None, flags, sp)
+                if rc != 0:
+                    raise cq.CQR2Error(rc, "cqr2_factor_ex")
+            for _ in range(warmup):
+                step()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                step()
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / steps
+            c = device_checks(torch, a, q, r)
+            res[name] = {"ms": round(ms, 4), "orthogonality": c["orthogonality"], "residual": c["residual"], "r": r}
+        r_rel = float(torch.linalg.norm(res["mixed"]["r"] - res["fp64"]["r"]) / torch.linalg.norm(res["fp64"]["r"]))
+        rows.append({
+            "kappa": kappa,
+            "fp64_ms": res["fp64"]["ms"], "mixed_ms": res["mixed"]["ms"],
+            "speedup": round(res["fp64"]["ms"] / res["mixed"]["ms"], 4),
+            "fp64_orthogonality": res["fp64"]["orthogonality"], "mixed_orthogonality": res["mixed"]["orthogonality"],
+            "fp64_residual": res["fp64"]["residual"], "mixed_residual": res["mixed"]["residual"],
+            "mixed_r_rel_to_fp64": r_rel,
+            "equal_orthogonality_gate": bool(res["fp64"]["orthogonality"] <= 1e-12
+                                             and res["mixed"]["orthogonality"] <= 1e-12),
+        })
+        log(f"mixed sweep kappa {kappa:g}: {rows[-1]}")
+    return {"workload": "mixed_262144x256", "m": m, "n": n, "steps": steps, "per_kappa": rows}
 
 
 def main():
@@ -259,6 +328,8 @@ def main():
     ap.add_argument("--calib-copy-gib", type=float, default=0.0,
                     help="also run a device copy of this many GiB (counter calibration under rocprofv3)")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-stream measurement")
+    ap.add_argument("--no-mixed-sweep", action="store_true",
+                    help="skip the FP64-vs-mixed comparison at 262144 x 256 over the condition numbers")
     ap.add_argument("--serve-only", action="store_true", help="only the served-stream measurement")
     ap.add_argument("--serve-requests", type=int, default=SERVE_REQUESTS)
     ap.add_argument("--serve-rate", type=float, default=SERVE_RATE)
@@ -419,6 +490,8 @@ def main():
         roof["avg_launch_ms"] = round(avg_ms, 5)
         roof["algorithmic_per_launch"] = by if bound == "hbm" else fl
         out["roofline"] = roof
+    if default_run and not args.no_mixed_sweep:
+        out["mixed_vs_fp64"] = mixed_sweep(cq, torch, steps=10, warmup=2)
     if default_run and not args.no_serve:
         out["serving"] = serve_stream(cq, torch, args.serve_requests, args.serve_rate, SERVE_SEED)
     if default_run and not args.no_cpu_baseline:

@@ -85,6 +85,12 @@ hipError_t launch_stream16_apply(const Stream16Plan& p, const double* A, int64_t
 hipError_t launch_stream16_apply_gram(const Stream16Plan& p, const double* A, int64_t m, int n, int64_t lda,
                                       const double* Upad, double* Q, int64_t ldq, double* partials,
                                       const int32_t* info, hipStream_t s);
+// Q = A U for n <= 256, U given as its zero-padded row-major upper image
+// (ld 256, upper_image_ld).  a_f32: A is FP32 (widened exactly), FP64
+// arithmetic into an FP64 Q; f32_math: FP64 A and U rounded to FP32, FP32
+// products and sums into an FP32 Q; neither: FP64.  Q may equal A (same type).
+hipError_t launch_apply256(int a_f32, int f32_math, const void* A, int64_t m, int n, int64_t lda,
+                           const double* Uimg, void* Q, int64_t ldq, const int32_t* info, hipStream_t s);
 // Fixed-order sum of the partials into the symmetric W (n x n, ldw).
 hipError_t launch_stream16_reduce(const Stream16Plan& p, const double* partials, int n, double* W, int64_t ldw,
                                   const int32_t* info, hipStream_t s);

@@ -713,6 +713,8 @@ hipError_t launch_upper_image(const double* X, int64_t ldx, int n, double* T, hi
 hipError_t launch_tall_gemm(int a_f32, const void* A, int64_t m, int n, int64_t lda, const double* Uimg, double* Q,
                             int64_t ldq, const int32_t* info, hipStream_t s) {
   if (m <= 0 || n <= 0) return hipSuccess;
+  // 128 < n <= 256: the MFMA 16x16x4 streaming kernel
+  if (n > 128 && n <= kTallUld) return launch_apply256(a_f32, 0, A, m, n, lda, Uimg, Q, ldq, info, s);
   const int64_t ld = upper_image_ld(n);
   dim3 grid((unsigned)((m + kTallRows - 1) / kTallRows), (unsigned)(ld / kTallUld));
   if (a_f32)
@@ -727,6 +729,7 @@ hipError_t launch_tall_gemm(int a_f32, const void* A, int64_t m, int n, int64_t 
 hipError_t launch_tall_gemm_f32(const double* A, int64_t m, int n, int64_t lda, const double* Uimg, float* Q,
                                 int64_t ldq, const int32_t* info, hipStream_t s) {
   if (m <= 0 || n <= 0) return hipSuccess;
+  if (n > 128 && n <= kTallUld) return launch_apply256(0, 1, A, m, n, lda, Uimg, Q, ldq, info, s);
   const int64_t ld = upper_image_ld(n);
   dim3 grid((unsigned)((m + kTallRows - 1) / kTallRows), (unsigned)(ld / kTallUld));
   hipLaunchKernelGGL((k_tall<double, true>), grid, dim3(512), 0, s, A, m, n, lda, Uimg, ld, (void*)Q, ldq, info);
