@@ -146,12 +146,27 @@ def test_mixed_workspace_holds_fp32_q1(gpu_lib):
 @pytest.mark.slow
 @pytest.mark.parametrize("kappa", sorted(MIXED_KAPPAS))
 def test_mixed_full_size_kappa_sweep(gpu_lib, kappa):
-    """The 262144 x 256 comparison problem at each condition number of the sweep."""
+    """The 262144 x 256 comparison problem at each condition number of the
+    sweep, both forms against the FP64 oracle (run with -s to print the row
+    of the per-kappa error table)."""
     from synth import workload_matrix
     a = workload_matrix("mixed_262144x256", kappa)
     q, r, info = mixed_factor(gpu_lib, a)
     assert info == 0
-    assert oracle.orthogonality(q) <= TOL_ORTH
-    assert oracle.residual(a, q, r) <= TOL_RES
+    qf, rf = gpu_lib.factor(to_dev(a))
+    qf, rf = to_host(qf), to_host(rf)
     q_ref, r_ref = oracle.cqr2(a)
+    row = {
+        "kappa": kappa,
+        "fp64": (oracle.orthogonality(qf), oracle.residual(a, qf, rf), oracle.rel_fro(rf, r_ref),
+                 oracle.rel_fro(qf, q_ref)),
+        "mixed": (oracle.orthogonality(q), oracle.residual(a, q, r), oracle.rel_fro(r, r_ref),
+                  oracle.rel_fro(q, q_ref)),
+    }
+    print(f"\nkappa {kappa:.0e}  (orth, resid, R rel, Q rel) vs the FP64 oracle: "
+          f"FP64 {' '.join(f'{x:.2e}' for x in row['fp64'])} | mixed {' '.join(f'{x:.2e}' for x in row['mixed'])}")
+    assert oracle.orthogonality(q) <= TOL_ORTH and oracle.orthogonality(qf) <= TOL_ORTH
+    assert oracle.residual(a, q, r) <= TOL_RES
+    assert oracle.residual(a, qf, rf) <= 1e-13
     assert oracle.rel_fro(r, r_ref) <= TOL_R
+    assert oracle.rel_fro(rf, r_ref) <= 1e-9
