@@ -90,17 +90,18 @@ hipError_t cholinv_recursive(double* W, int64_t ldw, int64_t n, double* R, int64
   double* T = (double*)work;
   double* gws = (double*)(work + (size_t)h * n2 * sizeof(double));
   const int sub = depth > 0 ? depth - 1 : 0;
-  // L11, Y11 = CholInv(A11)
+  // leading diagonal block: its factor and inverse, recursively
   CQR2_HIP(cholinv_recursive(W, ldw, h, R, ldr, Rinv, ldri, work, info, info_offset, s, sub));
   if (depth == 0) {
-    // L21 = A21 Y11ᵀ, kept as R12 = L21ᵀ = Y11 A21ᵀ = Rinv11ᵀ A21ᵀ
+    // off-diagonal block of the factor from the leading inverse, kept transposed
+    // in R's upper part: R12 = Rinv11ᵀ A21ᵀ
     CQR2_HIP(launch_gemm(1, 1, h, n2, h, 1.0, Rinv, ldri, W + h, ldw, 0.0, R12, ldr, GEMM_A_LOWER,
                          rec_splits(h, n2, h), gws, info, s));
   } else {
-    // L21 = A21 L11^{-T} by block substitution over the inverted diagonal
-    // blocks of Y11: per block b, T = A21(:, b) - L21(:, <b) L11(b, <b)ᵀ
-    // (= A21(:, b) - R12(<b, :)ᵀ R11(<b, b)), then R12(b, :) = (T Y_bbᵀ)ᵀ =
-    // Rinv_bbᵀ Tᵀ.  T (n2 x width) lives in the scratch block.
+    // partial inverse: the same off-diagonal block by block substitution
+    // over the leading block's inverted diagonal blocks; for block b the
+    // columns of A21 minus the contribution of the blocks before it, times
+    // that block's inverse.  T (n2 x width) lives in the scratch block.
     Block blk[256];
     const int nb = inverse_blocks(h, sub, blk, 256);
     for (int i = 0; i < nb; ++i) {
@@ -114,19 +115,20 @@ hipError_t cholinv_recursive(double* W, int64_t ldw, int64_t n, double* R, int64
                            GEMM_A_LOWER, 1, nullptr, info, s));
     }
   }
-  // A22 - L21 L21ᵀ = A22 - R12ᵀ R12 (lower triangle)
+  // trailing Schur complement (lower triangle): A22 - R12ᵀ R12
   CQR2_HIP(launch_gemm(1, 0, n2, n2, h, -1.0, R12, ldr, R12, ldr, 1.0, W22, ldw, GEMM_C_LOWER,
                        rec_splits(n2, n2, h), gws, info, s));
-  // L22, Y22 = CholInv(A22 - L21 L21ᵀ)
+  // trailing diagonal block: factor and inverse of the Schur complement
   CQR2_HIP(cholinv_recursive(W22, ldw, n2, R22, ldr, Ri22, ldri, work, info, info_offset + (int)h, s, sub));
   if (depth == 0) {
-    // Y21 = -Y22 (L21 Y11): in the transposed factors, Rinv12 = -(Rinv11 R12) Rinv22
+    // off-diagonal block of the inverse from the two diagonal inverses and
+    // R12: Rinv12 = -(Rinv11 R12) Rinv22
     CQR2_HIP(launch_gemm(0, 0, h, n2, h, 1.0, Rinv, ldri, R12, ldr, 0.0, T, h, GEMM_A_UPPER, rec_splits(h, n2, h),
                          gws, info, s));
     CQR2_HIP(launch_gemm(0, 0, h, n2, n2, -1.0, T, h, Ri22, ldri, 0.0, Ri12, ldri, GEMM_B_UPPER,
                          rec_splits(h, n2, n2), gws, info, s));
   } else {
-    CQR2_HIP(zero_block(Ri12, ldri, h, n2, s));  // Y21 is not formed at this level
+    CQR2_HIP(zero_block(Ri12, ldri, h, n2, s));  // the inverse's off-diagonal block is not formed at this level
   }
   // strictly lower blocks of the triangular factors
   CQR2_HIP(zero_block(R + h, ldr, n2, h, s));
