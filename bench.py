@@ -138,10 +138,11 @@ def cpu_baseline(a, budget_s: float):
 # rate); the rate is pinned well below the measured closed-loop capacity.
 SERVE_REQUESTS = 2000
 SERVE_SEED = 5
-SERVE_RATE = 2500.0            # requests per second (open loop), about 0.3 of the closed-loop capacity
+SERVE_RATE = 2500.0            # requests per second (open loop), about 0.2 of the closed-loop capacity
 SERVE_ARENA = 16 << 30         # workspace arena of the server, bytes
 SERVE_BUDGET = 64 << 30        # in-flight footprint budget (A, Q, R, workspace), bytes
 SERVE_SLOTS = 256
+SERVE_SUBMIT_PER_STEP = 64     # submissions between two server steps, at most
 
 
 def device_checks(torch, a, q, r, x=None, b=None):
@@ -201,7 +202,8 @@ def serve_stream(cq, torch, count: int, rate: float, seed: int):
             i = 0
             while len(done) < count:
                 now = (time.perf_counter() - h0) * 1e3
-                while i < count and arrivals_ms[i] <= now:
+                batch_end = i + SERVE_SUBMIT_PER_STEP   # the first launch need not wait for every submission
+                while i < min(count, batch_end) and arrivals_ms[i] <= now:
                     if with_lstsq and i in lsq:
                         sv.submit_lstsq(i, mats[i], lsq[i][0], lsq[i][1], qs[i], rs[i])
                     else:
@@ -221,12 +223,15 @@ def serve_stream(cq, torch, count: int, rate: float, seed: int):
     log(f"serving closed loop: {closed}")
     opened = run([r.arrival_s * 1e3 for r in reqs])
     log(f"serving open loop at {rate:.0f}/s: {opened}")
-    # the same stream time-compressed to 0.8 of the measured capacity
-    hi_rate = round(0.8 * closed["solves_per_s"], -2)
-    scale = rate / hi_rate if hi_rate > 0 else 1.0
-    high = run([r.arrival_s * 1e3 * scale for r in reqs])
-    high["rate_per_s"] = hi_rate
-    log(f"serving open loop at {hi_rate:.0f}/s: {high}")
+    # the same stream time-scaled to 0.5 and 0.8 of the measured capacity C
+    at_frac = {}
+    for frac in (0.5, 0.8):
+        r_frac = round(frac * closed["solves_per_s"], -2)
+        scale = rate / r_frac if r_frac > 0 else 1.0
+        res = run([r.arrival_s * 1e3 * scale for r in reqs])
+        res["rate_per_s"] = r_frac
+        at_frac[frac] = res
+        log(f"serving open loop at {r_frac:.0f}/s ({frac} C): {res}")
 
     # mixed request types: a quarter of the stream are least-squares solves
     mixed = run([r.arrival_s * 1e3 for r in reqs], with_lstsq=True)
@@ -250,7 +255,7 @@ def serve_stream(cq, torch, count: int, rate: float, seed: int):
         "requests": count, "rate_per_s": rate, "seed": seed,
         "mix": "m log-uniform [1024,131072], n in {16,32,64,128,256}, kappa log-uniform [1e1,1e6]",
         "solves_per_s": opened["solves_per_s"], "p50_ms": opened["p50_ms"], "p99_ms": opened["p99_ms"],
-        "closed_loop": closed, "open_loop": opened, "open_loop_0.8C": high, "open_loop_lstsq_mix": mixed,
+        "closed_loop": closed, "open_loop": opened, "open_loop_0.5C": at_frac[0.5], "open_loop_0.8C": at_frac[0.8], "open_loop_lstsq_mix": mixed,
         "device_check_sample": checked,
         "slots": SERVE_SLOTS, "arena_bytes": SERVE_ARENA, "footprint_budget": SERVE_BUDGET,
     }

@@ -259,10 +259,12 @@ size_t cqr2_batched_workspace_size(const cqr2_problem* probs, int32_t count, uin
 /*
  * cqr2_factor_batched — CholeskyQR2 (Algorithm 5, FP64) of `count` independent
  * problems of any shapes, enqueued on `stream`.  probs: host array, read
- * during the call only.  Problems with n <= 128 advance together: six launches
+ * during the call only.  Problems with n <= 256 advance together: launches
  * of one multi-problem kernel, each moving every problem through one phase
- * (Gram, CholInv, Q = A R^-1; twice; R = R2 R1 with the last).  Problems with
- * n > 128 run the tiled path one after another on the same stream.  work:
+ * (Gram, CholInv, Q = A R^-1; twice; R = R2 R1 with the last; six phases for
+ * n <= 128, eight for 128 < n <= 256, where the sum of the partial Grams is a
+ * phase of its own and CholInv splits W once at 128).  Problems with n > 256
+ * run the tiled path one after another on the same stream.  work:
  * >= cqr2_batched_workspace_size bytes, 256-byte aligned, device.  The task
  * tables are staged through library-owned pinned host memory (the call may
  * wait for an earlier call's staging buffer to be consumed).  Results equal
@@ -279,15 +281,18 @@ int cqr2_factor_batched(const cqr2_problem* probs, int32_t count, void* work, si
  * (first come, first served) while an active slot is free, the workspace arena
  * has room and the in-flight footprint (bytes of A, Q, R and workspace of
  * every admitted, unfinished request) stays within the budget; then it
- * launches ONE multi-problem kernel that advances every active n <= 128
+ * launches ONE multi-problem kernel that advances every active n <= 256
  * request by one phase, so requests admitted at different times share each
- * launch and a request finishes six steps after its admission.  Requests with
- * n > 128 run the tiled path on further streams of the server (round
+ * launch and a request finishes six (n <= 128) or eight (128 < n <= 256)
+ * steps after its admission.  A step first waits (on the host) until at most
+ * one of its earlier launches is still pending on the GPU, so each launch
+ * carries every request admitted up to then.  Requests with n > 256 run the
+ * tiled path on further streams of the server (round
  * robin) as soon as they are admitted, overlapping the steps.  There are one
  * fewer of them than the process's hardware queues (the GPU_MAX_HW_QUEUES
  * environment variable that HIP reads, default 4: three streams), so the
- * step stream keeps a queue of its own.  Nothing blocks on the GPU except when
- * the host runs more than a few steps ahead (pinned task-table ring).
+ * step stream keeps a queue of its own.  Apart from that wait, nothing blocks
+ * on the GPU.
  * Completion times are HIP event times in milliseconds since the last
  * cqr2_server_clock call.  A, Q and R stay owned by the caller and must stay
  * valid until the request is reported done by cqr2_server_poll.  A (and B) are

@@ -87,8 +87,9 @@ __device__ __forceinline__ double cholinv_src(const CholInvSrc& s, int p, int q)
 // B = 1 is the column-by-column form.
 //
 // Threads tid < G*G do the work; any further threads of the workgroup run
-// the same loop as shadows (same barriers, no stores) so the body can sit in
-// a workgroup larger than the grid.  colbuf: 2 * B * G * T doubles of LDS.
+// the same loop as shadows (the same barriers and pivot tests, no element
+// updates, no stores) so the body can sit in a workgroup larger than the
+// grid.  colbuf: 2 * B * G * T doubles of LDS.
 template <int T, int G, int B>
 __device__ __forceinline__ void cholinv_body(const CholInvSrc& src, int n, double* __restrict__ R, int64_t ldr,
                                              double* __restrict__ Rinv, int64_t ldri, double* __restrict__ Upad,
@@ -168,74 +169,78 @@ __device__ __forceinline__ void cholinv_body(const CholInvSrc& src, int n, doubl
           fail = bad;
           break;
         }
-        // rows: v(p); the same recurrence gives L(p, j) below the block and
-        // Y(j, p) above it; rows inside the block take Yb
-        double v[T][B];
-#pragma unroll
-        for (int a = 0; a < T; ++a) {
-          const int p = r + G * a;
-#pragma unroll
-          for (int jj = 0; jj < B; ++jj) {
-            double t = buf[jj][r * T + a];
-#pragma unroll
-            for (int ii = 0; ii < jj; ++ii) t = fma(-Lb[jj][ii], v[a][ii], t);
-            v[a][jj] = t * y[jj];
-          }
-          const int pp = p - j0;  // register arrays take compile-time indices only
-#pragma unroll
-          for (int i = 0; i < B; ++i)
-            if (pp == i) {
-#pragma unroll
-              for (int jj = 0; jj < B; ++jj) v[a][jj] = jj >= i ? Yb[jj][i] : 0.0;
-            }
-        }
-        // columns right of the block: L(q, j)
-        double lq[T][B];
-#pragma unroll
-        for (int b = jb; b < T; ++b) {
-#pragma unroll
-          for (int jj = 0; jj < B; ++jj) {
-            double t = buf[jj][c * T + b];
-#pragma unroll
-            for (int ii = 0; ii < jj; ++ii) t = fma(-Lb[jj][ii], lq[b][ii], t);
-            lq[b][jj] = t * y[jj];
-          }
-        }
-        // owners finalize the block's columns
-#pragma unroll
-        for (int kk = 0; kk < B; ++kk) {
-          if (c != jc0 + kk) continue;
+        // shadow threads (beyond the G x G grid) skip the per-element work;
+        // they keep only the barriers and the pivot test above
+        if (worker) {
+          // rows: v(p); the same recurrence gives L(p, j) below the block and
+          // Y(j, p) above it; rows inside the block take Yb
+          double v[T][B];
 #pragma unroll
           for (int a = 0; a < T; ++a) {
-            const int pp = r + G * a - j0;
-            double val = v[a][kk];  // L(p, j) below the block, Y(j, p) above it
-#pragma unroll
-            for (int i = 0; i < B; ++i)
-              if (pp == i) val = i > kk ? Lb[i][kk] : (i == kk ? sd[kk] : Yb[kk][i]);
-            M[a][jb] = val;
-          }
-        }
-        // rank-B update of every element right of the block: below the
-        // diagonal with v(p) = L(p, .), above it with Y(., p), which is v(p)
-        // for rows above or inside the block and zero for rows below it
-        const bool right_of_block = c >= jc0 + B;  // column c + G jb lies right of the block
-        const bool low_diag = r >= c;              // element (a, a) of this thread lies on or below the diagonal
-#pragma unroll
-        for (int a = 0; a < T; ++a) {
-          const bool row_up = r + G * a < j0 + B;
-          double vu[B];
-#pragma unroll
-          for (int jj = 0; jj < B; ++jj) vu[jj] = row_up ? v[a][jj] : 0.0;
-#pragma unroll
-          for (int b = jb; b < T; ++b) {
-            if (b == jb && !right_of_block) continue;
-            double t = M[a][b];
+            const int p = r + G * a;
 #pragma unroll
             for (int jj = 0; jj < B; ++jj) {
-              const double f = a > b ? v[a][jj] : (a < b ? vu[jj] : (low_diag ? v[a][jj] : vu[jj]));
-              t = fma(-f, lq[b][jj], t);
+              double t = buf[jj][r * T + a];
+#pragma unroll
+              for (int ii = 0; ii < jj; ++ii) t = fma(-Lb[jj][ii], v[a][ii], t);
+              v[a][jj] = t * y[jj];
             }
-            M[a][b] = t;
+            const int pp = p - j0;  // register arrays take compile-time indices only
+#pragma unroll
+            for (int i = 0; i < B; ++i)
+              if (pp == i) {
+#pragma unroll
+                for (int jj = 0; jj < B; ++jj) v[a][jj] = jj >= i ? Yb[jj][i] : 0.0;
+              }
+          }
+          // columns right of the block: L(q, j)
+          double lq[T][B];
+#pragma unroll
+          for (int b = jb; b < T; ++b) {
+#pragma unroll
+            for (int jj = 0; jj < B; ++jj) {
+              double t = buf[jj][c * T + b];
+#pragma unroll
+              for (int ii = 0; ii < jj; ++ii) t = fma(-Lb[jj][ii], lq[b][ii], t);
+              lq[b][jj] = t * y[jj];
+            }
+          }
+          // owners finalize the block's columns
+#pragma unroll
+          for (int kk = 0; kk < B; ++kk) {
+            if (c != jc0 + kk) continue;
+#pragma unroll
+            for (int a = 0; a < T; ++a) {
+              const int pp = r + G * a - j0;
+              double val = v[a][kk];  // L(p, j) below the block, Y(j, p) above it
+#pragma unroll
+              for (int i = 0; i < B; ++i)
+                if (pp == i) val = i > kk ? Lb[i][kk] : (i == kk ? sd[kk] : Yb[kk][i]);
+              M[a][jb] = val;
+            }
+          }
+          // rank-B update of every element right of the block: below the
+          // diagonal with v(p) = L(p, .), above it with Y(., p), which is v(p)
+          // for rows above or inside the block and zero for rows below it
+          const bool right_of_block = c >= jc0 + B;  // column c + G jb lies right of the block
+          const bool low_diag = r >= c;              // element (a, a) of this thread lies on or below the diagonal
+#pragma unroll
+          for (int a = 0; a < T; ++a) {
+            const bool row_up = r + G * a < j0 + B;
+            double vu[B];
+#pragma unroll
+            for (int jj = 0; jj < B; ++jj) vu[jj] = row_up ? v[a][jj] : 0.0;
+#pragma unroll
+            for (int b = jb; b < T; ++b) {
+              if (b == jb && !right_of_block) continue;
+              double t = M[a][b];
+#pragma unroll
+              for (int jj = 0; jj < B; ++jj) {
+                const double f = a > b ? v[a][jj] : (a < b ? vu[jj] : (low_diag ? v[a][jj] : vu[jj]));
+                t = fma(-f, lq[b][jj], t);
+              }
+              M[a][b] = t;
+            }
           }
         }
       }

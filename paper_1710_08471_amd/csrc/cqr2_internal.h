@@ -207,15 +207,23 @@ int inverse_blocks(int64_t n, int depth, Block* out, int cap);
 // Adds s = 11 (m n + n (n + 1)) 2^-53 trace(W) to the diagonal of W (shifted CholeskyQR).
 hipError_t launch_shift_diag(double* W, int64_t ldw, int64_t n, int64_t m, const int32_t* info, hipStream_t s);
 
-// ---- multi-problem step (batched and serving paths, n <= 128) -------------
-// One launch advances every listed problem by one phase of CholeskyQR2:
+// ---- multi-problem step (batched and serving paths, n <= 256) -------------
+// One launch advances every listed problem by one phase of CholeskyQR2.
+// n <= 128 (six phases):
 //   0 Gram(A) partials, 1 CholInv(sum of partials) -> R1, U1 = R1^-1,
 //   2 Q = A U1, 3 Gram(Q) partials, 4 CholInv -> R2, U2, 5 Q = Q U2 and R = R2 R1.
+// 128 < n <= 256 (eight phases):
+//   0 Gram(A) partials, 1 their sum W, 2 CholInv(W) -> R1, U1, 3 Q = A U1,
+//   4 Gram(Q) partials, 5 their sum, 6 CholInv -> R2, U2, 7 Q = Q U2 and
+//   R = R2 R1.
 // Workgroups are dealt to the problems by the table (task t owns workgroups
 // [wg0, wg0 + nwg)); tasks are sorted by wg0.
 constexpr int kStepThreads = 512;
 constexpr int kStepStages = 64;  // 64-row stages per Gram / Q workgroup (4096 rows)
 constexpr int kStepPhases = 6;
+constexpr int kStepMaxN = 256;
+constexpr int kStepWidePhases = 8;
+constexpr int kStepWideStages = 64;  // 32-row stages per wide Gram / Q workgroup (2048 rows)
 struct StepTask {
   const double* A;
   int64_t lda;
@@ -223,18 +231,29 @@ struct StepTask {
   int64_t ldq;
   double* R;
   int64_t ldr;
-  int32_t* user_info;  // optional; written in phase 5
+  int32_t* user_info;  // optional; written in the last phase
   char* ws;            // the problem's workspace (StepLayout)
   int64_t m;
   int32_t n, phase, wg0, nwg;
 };
+// Workspace of one problem.  n <= 128: the partial Grams in the 4x4-block
+// layout, R1, R2 (n x n) and the padded images U1, U2 (np x np, row-major).
+// 128 < n <= 256: the partial Grams in the 16x16-tile layout, then 256 x 256
+// blocks: W, R1, R2 and R^-1 scratch (column-major, ld 256), U1, U2 (row-major
+// images), and one temporary.
 struct StepLayout {
   int np = 0, ng = 0, nblk = 0, splits = 0;
   size_t off_info = 0, off_part = 0, off_r1 = 0, off_r2 = 0, off_u1 = 0, off_u2 = 0, total = 0;
+  size_t off_w = 0, off_ri = 0, off_t = 0;  // 128 < n <= 256 only
 };
 StepLayout step_layout(int64_t m, int64_t n);
-// Workgroups of phase `phase` for an m-row problem.
-int step_workgroups(int64_t m, int phase);
+// Phases of an n-column problem (n <= kStepMaxN).
+int step_phases(int64_t n);
+// Workgroups of phase `phase` for an m x n problem.
+int step_workgroups(int64_t m, int64_t n, int phase);
+// Rough duration of one workgroup of phase `phase` (microseconds, full row
+// chunk, measured on MI355X); only the order of these values is used.
+double step_wg_cost(int64_t n, int phase);
 hipError_t launch_step(const StepTask* d_tasks, int ntasks, int total_wgs, hipStream_t s);
 
 // ---- least squares on a finished factorization ---------------------------

@@ -1,6 +1,6 @@
 // Many CholeskyQR2 problems per launch: the batched entry point and the
 // continuous-batching server (host side).  Both drive the multi-problem step
-// kernel (cqr2_step.hip) for n <= 128 and the tiled path for larger n.  Server
+// kernel (cqr2_step.hip) for n <= 256 and the tiled path for larger n.  Server
 // requests are QR factorizations or least-squares solves (the factorization
 // followed by X = R^{-1} Qᵀ B).
 //
@@ -23,7 +23,7 @@
 
 namespace {
 
-constexpr int64_t kStepMaxN = 128;
+using cqr2::kStepMaxN;
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -57,7 +57,7 @@ cqr2::StepTask make_task(const cqr2_problem& p, char* ws, int phase, int wg0) {
   t.n = (int32_t)p.n;
   t.phase = phase;
   t.wg0 = wg0;
-  t.nwg = cqr2::step_workgroups(p.m, phase);
+  t.nwg = cqr2::step_workgroups(p.m, p.n, phase);
   return t;
 }
 
@@ -191,26 +191,34 @@ struct cqr2_server {
     std::vector<size_t> offs;
   };
 
-  // Streams for n > 128 requests: one fewer than the process's hardware
+  // Streams for n > 256 requests: one fewer than the process's hardware
   // queues (GPU_MAX_HW_QUEUES, HIP's default 4), so that with the step stream
   // every stream has a queue of its own and the steps never wait behind a
   // large request's kernels.
   static constexpr int kMaxLargeStreams = 31;
   int n_large = 3;
   hipStream_t stream = nullptr;                 // steps
-  hipStream_t large[kMaxLargeStreams] = {};     // n > 128 requests, round robin
+  hipStream_t large[kMaxLargeStreams] = {};     // n > 256 requests, round robin
   int large_next = 0;
   char* arena_base = nullptr;
   Arena arena;
   size_t budget = 0, in_flight_bytes = 0;
   int max_active = 0;
   std::deque<Req> queue;
-  std::vector<Active> active;         // n <= 128, in phase order of admission
+  std::vector<Active> active;         // n <= 256, in phase order of admission
   int n_large_running = 0;
   std::deque<Finishing> finishing;
   std::vector<std::pair<int64_t, double>> done;
   std::vector<hipEvent_t> event_pool;
   hipEvent_t t0 = nullptr;
+  // Launch pacing: a step first waits until fewer than kInFlight of its
+  // earlier launches are pending on the GPU, then reaps, admits and launches.
+  // The host thus stays close behind the GPU, and each launch carries every
+  // request admitted up to then instead of a few requests each.
+  static constexpr int kInFlight = 2;
+  hipEvent_t pace[kInFlight] = {};
+  bool pace_live[kInFlight] = {};
+  int pace_next = 0;
   // Recorded on `stream` when a large request is admitted; the large stream
   // waits on it, so the request reads A (and B) only after everything the
   // caller enqueued on `stream` before the step that admits it.
@@ -219,6 +227,7 @@ struct cqr2_server {
   std::vector<char*> dev_tables;      // one device table per ring slot
   int dev_next = 0;
   std::vector<cqr2::StepTask> table;
+  std::vector<size_t> order;
 
   hipEvent_t get_event() {
     if (!event_pool.empty()) {
@@ -292,14 +301,25 @@ struct cqr2_server {
   }
 
   int step() {
+    if (pace_live[pace_next]) {
+      if (hipEventSynchronize(pace[pace_next]) != hipSuccess) return CQR2_ERR_HIP;
+      pace_live[pace_next] = false;
+    }
     int rc = reap();
     if (rc) return rc;
     rc = admit();
     if (rc) return rc;
     if (active.empty()) return 0;
+    // longest workgroups first, so that the launch ends on short ones
+    order.resize(active.size());
+    for (size_t i = 0; i < active.size(); ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
+      return cqr2::step_wg_cost(active[x].r.p.n, active[x].phase) > cqr2::step_wg_cost(active[y].r.p.n, active[y].phase);
+    });
     table.clear();
     int wg = 0;
-    for (const Active& a : active) {
+    for (size_t i : order) {
+      const Active& a = active[i];
       table.push_back(make_task(a.r.p, arena_base + a.ws_off, a.phase, wg));
       wg += table.back().nwg;
     }
@@ -312,7 +332,7 @@ struct cqr2_server {
     if (rc) return rc;
     // least-squares requests whose factorization this step completes: the solve
     for (const Active& a : active) {
-      if (a.phase != cqr2::kStepPhases - 1 || a.r.nrhs == 0) continue;
+      if (a.phase != cqr2::step_phases(a.r.p.n) - 1 || a.r.nrhs == 0) continue;
       const cqr2_problem& p = a.r.p;
       const cqr2::StepLayout L = cqr2::step_layout(p.m, p.n);
       char* ws = arena_base + a.ws_off;
@@ -321,13 +341,16 @@ struct cqr2_server {
                                     (const int32_t*)(ws + L.off_info), stream));
       if (rc) return rc;
     }
+    if (hipEventRecord(pace[pace_next], stream) != hipSuccess) return CQR2_ERR_HIP;
+    pace_live[pace_next] = true;
+    pace_next = (pace_next + 1) % kInFlight;
     hipEvent_t ev = get_event();
     if (ev == nullptr || hipEventRecord(ev, stream) != hipSuccess) return CQR2_ERR_HIP;
     Finishing fin{ev, {}, {}};
     std::vector<Active> still;
     still.reserve(active.size());
     for (Active& a : active) {
-      if (a.phase == cqr2::kStepPhases - 1) {
+      if (a.phase == cqr2::step_phases(a.r.p.n) - 1) {
         fin.reqs.push_back(a.r);
         fin.offs.push_back(a.ws_off);
       } else {
@@ -350,13 +373,13 @@ extern "C" {
 size_t cqr2_batched_workspace_size(const cqr2_problem* probs, int32_t count, uint32_t flags) {
   if (probs == nullptr || count < 0 || flags != CQR2_FP64) return 0;
   size_t total = 0;
-  int64_t nsmall = 0;
+  int64_t ntasks = 0;
   for (int32_t i = 0; i < count; ++i) {
     if (cqr2_problem_check(&probs[i]) != 0) return 0;
     total += problem_workspace(probs[i]);
-    if (probs[i].n > 0 && probs[i].n <= kStepMaxN) ++nsmall;
+    if (probs[i].n > 0 && probs[i].n <= kStepMaxN) ntasks += cqr2::step_phases(probs[i].n);
   }
-  total += align_up((size_t)nsmall * cqr2::kStepPhases * sizeof(cqr2::StepTask));
+  total += align_up((size_t)ntasks * sizeof(cqr2::StepTask));
   return total ? total : kAlign;
 }
 
@@ -371,11 +394,17 @@ int cqr2_factor_batched(const cqr2_problem* probs, int32_t count, void* work, si
   if (work == nullptr || ((uintptr_t)work % kAlign) != 0) return -3;
   if (work_bytes < cqr2_batched_workspace_size(probs, count, flags)) return -4;
   hipStream_t s = (hipStream_t)stream;
-  // layout: task tables (6 phases), then one workspace per problem
+  // layout: the task tables of every phase, then one workspace per problem
   std::vector<int32_t> small;
+  int64_t ntasks = 0;
+  int phases = 0;
   for (int32_t i = 0; i < count; ++i)
-    if (probs[i].n > 0 && probs[i].n <= kStepMaxN) small.push_back(i);
-  const size_t tab_bytes = align_up(small.size() * cqr2::kStepPhases * sizeof(cqr2::StepTask));
+    if (probs[i].n > 0 && probs[i].n <= kStepMaxN) {
+      small.push_back(i);
+      ntasks += cqr2::step_phases(probs[i].n);
+      phases = std::max(phases, cqr2::step_phases(probs[i].n));
+    }
+  const size_t tab_bytes = align_up((size_t)ntasks * sizeof(cqr2::StepTask));
   char* base = (char*)work;
   std::vector<size_t> off(count);
   size_t cur = tab_bytes;
@@ -384,14 +413,19 @@ int cqr2_factor_batched(const cqr2_problem* probs, int32_t count, void* work, si
     cur += problem_workspace(probs[i]);
   }
   if (!small.empty()) {
+    // launch ph runs phase ph of every problem that has one
     std::vector<cqr2::StepTask> tabs;
-    std::vector<int> wgs(cqr2::kStepPhases, 0);
-    tabs.reserve(small.size() * cqr2::kStepPhases);
-    for (int ph = 0; ph < cqr2::kStepPhases; ++ph)
+    std::vector<int> wgs(phases, 0), first(phases, 0), count_ph(phases, 0);
+    tabs.reserve(ntasks);
+    for (int ph = 0; ph < phases; ++ph) {
+      first[ph] = (int)tabs.size();
       for (int32_t i : small) {
+        if (ph >= cqr2::step_phases(probs[i].n)) continue;
         tabs.push_back(make_task(probs[i], base + off[i], ph, wgs[ph]));
         wgs[ph] += tabs.back().nwg;
       }
+      count_ph[ph] = (int)tabs.size() - first[ph];
+    }
     {
       std::lock_guard<std::mutex> g(g_batched_mu);
       if (g_batched_ring == nullptr) g_batched_ring = new TableRing(4);
@@ -399,8 +433,8 @@ int cqr2_factor_batched(const cqr2_problem* probs, int32_t count, void* work, si
       if (rc) return rc;
     }
     const cqr2::StepTask* dt = (const cqr2::StepTask*)base;
-    for (int ph = 0; ph < cqr2::kStepPhases; ++ph) {
-      const int rc = to_code(cqr2::launch_step(dt + (size_t)ph * small.size(), (int)small.size(), wgs[ph], s));
+    for (int ph = 0; ph < phases; ++ph) {
+      const int rc = to_code(cqr2::launch_step(dt + first[ph], count_ph[ph], wgs[ph], s));
       if (rc) return rc;
     }
   }
@@ -432,6 +466,8 @@ int cqr2_server_create(size_t arena_bytes, size_t footprint_budget, int32_t max_
   };
   if (hipMalloc((void**)&sv->arena_base, arena_bytes) != hipSuccess) return fail(CQR2_ERR_HIP);
   if (hipEventCreateWithFlags(&sv->order_ev, hipEventDisableTiming) != hipSuccess) return fail(CQR2_ERR_HIP);
+  for (auto& e : sv->pace)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return fail(CQR2_ERR_HIP);
   sv->arena.reset(arena_bytes);
   int hw_queues = 4;  // HIP's default hardware queues per process
   if (const char* e = std::getenv("GPU_MAX_HW_QUEUES")) {
@@ -466,6 +502,8 @@ int cqr2_server_destroy(cqr2_server* s) {
   for (hipEvent_t e : s->event_pool) (void)hipEventDestroy(e);
   if (s->t0) (void)hipEventDestroy(s->t0);
   if (s->order_ev) (void)hipEventDestroy(s->order_ev);
+  for (hipEvent_t e : s->pace)
+    if (e) (void)hipEventDestroy(e);
   if (s->arena_base) (void)hipFree(s->arena_base);
   delete s;
   return 0;

@@ -21,6 +21,9 @@ MIX = [  # (m, n, kappa, seed): every n class, ragged m, chunk boundaries, one t
     (5000, 1, 1.0, 101), (3000, 7, 1e2, 102), (4096, 16, 1e3, 103), (10000, 32, 1e4, 104),
     (777, 33, 1e3, 105), (20000, 64, 1e6, 106), (9000, 100, 1e5, 107), (8193, 128, 1e6, 108),
     (4096 * 3 + 17, 96, 1e4, 109), (128, 128, 1e2, 110), (5000, 200, 1e4, 111), (64, 64, 10.0, 112),
+    # 128 < n <= 256 (eight-phase step): 2048-row chunks and a ragged tail, m = n, both blocks ragged
+    (3000, 256, 1e5, 116), (2048 * 4 + 1, 129, 1e3, 117), (256, 256, 1e2, 118), (2047, 250, 1e6, 119),
+    (6000, 300, 1e3, 120),
 ]
 
 
@@ -46,7 +49,7 @@ def test_batched_mix_matches_oracle(gpu_lib):
 
 
 def test_batched_alone_equals_in_mix(gpu_lib):
-    mats = [gdv_matrix(m, n, k, s) for (m, n, k, s) in MIX[:9]]
+    mats = [gdv_matrix(m, n, k, s) for (m, n, k, s) in MIX]
     mixed = gpu_lib.factor_batched([to_dev(a) for a in mats])
     for a, (qm, rm) in zip(mats, mixed):
         (qa, ra), = gpu_lib.factor_batched([to_dev(a)])
@@ -60,13 +63,18 @@ def test_batched_padded_lda_and_breakdown(gpu_lib):
     a2 = gdv_matrix(3000, 20, 10.0, 114)
     a2[:, 4] = 0.0
     a3 = gdv_matrix(2500, 130, 10.0, 115)
-    a3[:, 129] = 0.0
-    infos = torch.full((3,), -5, dtype=torch.int32, device="cuda")
-    outs = gpu_lib.factor_batched([to_dev(a1, ld=6001 + 15), to_dev(a2), to_dev(a3)], infos)
-    assert infos.tolist() == [0, 5, 130]
+    a3[:, 129] = 0.0              # breakdown in the second diagonal block of the wide CholInv
+    a4 = gdv_matrix(3000, 256, 10.0, 116)
+    a4[:, 40] = 0.0               # ... and in the first
+    a5 = gdv_matrix(4100, 200, 1e4, 117)
+    infos = torch.full((5,), -5, dtype=torch.int32, device="cuda")
+    outs = gpu_lib.factor_batched([to_dev(a1, ld=6001 + 15), to_dev(a2), to_dev(a3), to_dev(a4),
+                                   to_dev(a5, ld=4100 + 9)], infos)
+    assert infos.tolist() == [0, 5, 130, 41, 0]
     check(a1, to_host(outs[0][0]), to_host(outs[0][1]), 1e3)
-    assert np.all(np.isnan(to_host(outs[1][1])))
-    assert np.all(np.isnan(to_host(outs[2][1])))
+    for k in (1, 2, 3):
+        assert np.all(np.isnan(to_host(outs[k][1])))
+    check(a5, to_host(outs[4][0]), to_host(outs[4][1]), 1e4)
 
 
 def _serve(lib, mats, arena, budget=0, max_active=64, arrivals_per_step=3):
@@ -113,11 +121,11 @@ def test_server_results_equal_alone(gpu_lib):
 
 
 def test_server_large_request_reads_after_callers_stream(gpu_lib):
-    """A request with n > 128 runs on one of the server's own streams; it must
+    """A request with n > 256 runs on one of the server's own streams; it must
     still read A only after the caller's earlier work on the server's stream
     (here a spin kernel and then the copy that fills A)."""
     import torch
-    m, n = 20000, 200
+    m, n = 20000, 300
     a = gdv_matrix(m, n, 1e4, 140)
     src = to_dev(a)
     A = gpu_lib.empty_colmajor(m, n, device="cuda")
