@@ -44,17 +44,19 @@ KERNEL_SOURCE = {
     "k_gemm": ["cqr2_gemm.hip"],
     "k_gemm_f32": ["cqr2_gemm.hip"],
     "k_gemm_reduce": ["cqr2_gemm.hip"],
-    "k_gram_wide": ["cqr2_wide.hip", "sync_dev.h"],
-    "k_gram_wide_reduce": ["cqr2_wide.hip", "sync_dev.h"],
-    "k_syrk_tile": ["cqr2_wide.hip", "sync_dev.h"],
-    "k_syrk_reduce": ["cqr2_wide.hip", "sync_dev.h"],
-    "k_tall": ["cqr2_wide.hip", "sync_dev.h"],
-    "k_upper_image": ["cqr2_wide.hip", "sync_dev.h"],
-    "k_step": ["cqr2_step.hip", "gram_dev.h", "cholinv_dev.h", "apply_dev.h"],
-    "k_gram16": ["cqr2_stream16.hip", "sync_dev.h"],
-    "k_apply16": ["cqr2_stream16.hip", "sync_dev.h"],
-    "k_fused16": ["cqr2_stream16.hip", "sync_dev.h"],
-    "k_gram16_reduce": ["cqr2_stream16.hip", "sync_dev.h"],
+    "k_gram_wide": ["cqr2_wide.hip", "wide_dev.h", "sync_dev.h"],
+    "k_gram_wide_reduce": ["cqr2_wide.hip", "wide_dev.h", "sync_dev.h"],
+    "k_syrk_tile": ["cqr2_wide.hip", "wide_dev.h", "sync_dev.h"],
+    "k_syrk_reduce": ["cqr2_wide.hip", "wide_dev.h", "sync_dev.h"],
+    "k_tall": ["cqr2_wide.hip", "wide_dev.h", "sync_dev.h"],
+    "k_upper_image": ["cqr2_wide.hip", "wide_dev.h", "sync_dev.h"],
+    "k_step": ["cqr2_step.hip", "gram_dev.h", "cholinv_dev.h", "apply_dev.h", "stream16_dev.h", "wide_dev.h",
+               "sync_dev.h"],
+    "k_gram16": ["cqr2_stream16.hip", "stream16_dev.h", "sync_dev.h"],
+    "k_apply16": ["cqr2_stream16.hip", "stream16_dev.h", "sync_dev.h"],
+    "k_fused16": ["cqr2_stream16.hip", "stream16_dev.h", "sync_dev.h"],
+    "k_gram16_reduce": ["cqr2_stream16.hip", "stream16_dev.h", "sync_dev.h"],
+    "k_apply256": ["cqr2_stream16.hip", "stream16_dev.h", "sync_dev.h"],
 }
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
