@@ -94,12 +94,17 @@ def _find(dirpath: str, suffix: str) -> str:
     return hits[0]
 
 
-def stats_report(dirpath: str, command: str) -> str:
+def stats_report(dirpath: str, command: str, library_only: bool = False) -> str:
     path = _find(dirpath, "_kernel_stats.csv")
     rows = list(csv.DictReader(open(path)))
+    note = []
+    if library_only:
+        rows = [r for r in rows if short_name(r["Name"]).startswith("k_")]
+        note = ["(this library's kernels only; the input generator's kernels are left out, so pct is of the whole run)"]
     lines = [
         "rocprofv3 kernel statistics",
         f"command: {command}",
+        *note,
         "",
         f"{'kernel':<60} {'calls':>6} {'avg_us':>10} {'min_us':>10} {'max_us':>10} {'total_ms':>10} {'pct':>6}",
     ]
@@ -115,8 +120,10 @@ def stats_report(dirpath: str, command: str) -> str:
 
 def _counter_means(dirpath: str, counter: str):
     """{kernel: (mean value per dispatch, dispatches)}; the copy kernel's entry
-    is the calibration copy alone: the last of its dispatches with the largest
-    grid (the program's other copies, e.g. host-to-device staging, differ)."""
+    is the calibration copy alone: the dispatch with the largest count (the
+    calibration copy is the largest copy the program makes; its other copies,
+    host-to-device staging and the 512 MB matrix copies of the mixed sweep, are
+    smaller, and copies of different sizes can share one grid size)."""
     path = _find(dirpath, "_counter_collection.csv")
     vals = collections.defaultdict(list)
     copies = []
@@ -130,7 +137,7 @@ def _counter_means(dirpath: str, counter: str):
             vals[name].append(float(r["Counter_Value"]))
     out = {k: (sum(v) / len(v), len(v)) for k, v in vals.items()}
     if copies:
-        out[COPY_KERNEL] = (max(copies)[2], 1)
+        out[COPY_KERNEL] = (max(v for _, _, v in copies), 1)
     return out
 
 
@@ -210,6 +217,7 @@ def main():
     s.add_argument("dir")
     s.add_argument("--command", required=True)
     s.add_argument("--out", required=True)
+    s.add_argument("--library-only", action="store_true")
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
@@ -230,7 +238,7 @@ def main():
         print(text)
         return
     if a.cmd == "stats":
-        text = stats_report(a.dir, a.command)
+        text = stats_report(a.dir, a.command, a.library_only)
         with open(a.out, "w") as f:
             f.write(text)
         print(text)
