@@ -4,6 +4,7 @@
 // call, so invalid arguments never launch anything.
 #include "cqr2.h"
 #include "cqr2_internal.h"
+#include "ws_cache.h"
 
 #include <hip/hip_runtime.h>
 
@@ -149,17 +150,16 @@ cqr2::TimerHook timer_hook() {
 
 // ---- library-cached workspace for the entry points without a work argument --
 // One buffer per device, shared by cqr2_factor, cqr2_cholinv (n > 128),
-// cqr2_apply_rinv (n > 128) and cqr2_apply_rinv_f32.  A caller holds the lease
-// (and with it the lock) until its launches are enqueued, so no other thread
-// can replace the buffer between the lookup and the enqueue.  Growing it
-// synchronizes the device before the old buffer is freed, since work enqueued
-// earlier on any stream may still use it.
-struct CachedWs {
-  void* ptr = nullptr;
-  size_t bytes = 0;
+// cqr2_apply_rinv (n > 128) and cqr2_apply_rinv_f32 (ws_cache.h: the lease
+// keeps the lock until the launches are enqueued; growing waits for the
+// device before the old buffer is freed).
+struct HipDev {
+  static bool device(int* d) { return hipGetDevice(d) == hipSuccess; }
+  static bool sync() { return hipDeviceSynchronize() == hipSuccess; }
+  static bool alloc(void** p, size_t bytes) { return hipMalloc(p, bytes) == hipSuccess; }
+  static void release(void* p) { (void)hipFree(p); }
 };
-std::mutex g_ws_mu;
-std::vector<CachedWs> g_ws;  // per device
+cqr2::WorkspaceCache<HipDev> g_ws_cache;
 
 struct WsLease {
   std::unique_lock<std::mutex> lock;
@@ -168,26 +168,11 @@ struct WsLease {
 };
 
 WsLease cached_workspace(size_t bytes) {
+  auto c = g_ws_cache.acquire(bytes, kAlign);
   WsLease l;
-  l.lock = std::unique_lock<std::mutex>(g_ws_mu);
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) { l.err = CQR2_ERR_HIP; return l; }
-  if ((int)g_ws.size() <= dev) g_ws.resize(dev + 1);
-  CachedWs& w = g_ws[dev];
-  if (bytes == 0) bytes = kAlign;
-  if (w.bytes < bytes) {
-    if (w.ptr) {
-      if (hipDeviceSynchronize() != hipSuccess) { l.err = CQR2_ERR_HIP; return l; }
-      (void)hipFree(w.ptr);
-      w.ptr = nullptr;
-      w.bytes = 0;
-    }
-    void* p = nullptr;
-    if (hipMalloc(&p, bytes) != hipSuccess) { l.err = CQR2_ERR_HIP; return l; }
-    w.ptr = p;
-    w.bytes = bytes;
-  }
-  l.ptr = w.ptr;
+  l.lock = std::move(c.lock);
+  l.ptr = c.ptr;
+  l.err = c.ok ? 0 : CQR2_ERR_HIP;
   return l;
 }
 

@@ -19,8 +19,12 @@ namespace cqr2 {
 
 // Tile sizes: a workgroup computes a 64 x 64 block of C with 4 waves in a
 // 2 x 2 arrangement of 32 x 32 wave tiles; the reduction dimension is staged
-// through LDS in chunks of 16.
-constexpr int kGM = 64, kGN = 64, kGK = 16;
+// through LDS in chunks of kGK.
+#ifndef CQR2_GEMM_KC
+#define CQR2_GEMM_KC 16
+#endif
+constexpr int kGM = 64, kGN = 64, kGK = CQR2_GEMM_KC;
+constexpr int kGStage = kGK * kGM / 256;  // entries of each operand chunk per thread
 
 // One MFMA 4x4x4 (4 blocks) with the blocks as four groups of 4 rows:
 // lane l supplies op(A)(r0 + (l&15), k0 + (l>>4)) and op(B)(k0 + (l>>4), c0 + (l&3))
@@ -80,7 +84,7 @@ __device__ __forceinline__ void gemm_krange(const GemmArgs& g, int64_t i0, int64
   const int64_t sb = (int64_t)split * g.kchunk, se = sb + g.kchunk;
   kb = kb > sb ? kb : sb;
   ke = ke < se ? ke : se;
-  kb = (kb / 16) * 16;  // chunk-aligned start (entries below kb are zero by structure)
+  kb = (kb / kGK) * kGK;  // chunk-aligned start (entries below kb are zero by structure)
 }
 
 template <typename TA, typename TB>
@@ -99,32 +103,32 @@ __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;  // wave tile origin within the block
 
-  // Staging: each thread moves 4 entries of the A chunk and 4 of the B chunk.
-  double ra[4], rb[4];
+  // Staging: each thread moves kGStage entries of the A chunk and of the B chunk.
+  double ra[kGStage], rb[kGStage];
   auto gload = [&](int64_t k0) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int e = tid + 256 * t;  // 0 .. 1023
-      // A chunk 64 x 16: for op N walk rows fastest (coalesced), for op T walk k fastest.
+    for (int t = 0; t < kGStage; ++t) {
+      const int e = tid + 256 * t;
+      // A chunk 64 x kGK: for op N walk rows fastest (coalesced), for op T walk k fastest.
       int r, k;
-      if (g.transA) { k = e & 15; r = e >> 4; } else { r = e & 63; k = e >> 6; }
+      if (g.transA) { k = e % kGK; r = e / kGK; } else { r = e & 63; k = e >> 6; }
       const int64_t gi = i0 + r, gk = k0 + k;
       ra[t] = (gi < g.M && gk < ke && a_in_triangle(g, gi, gk)) ? load_opA<TA>(g, gi, gk) : 0.0;
       int kk, c;
-      if (g.transB) { c = e & 63; kk = e >> 6; } else { kk = e & 15; c = e >> 4; }
+      if (g.transB) { c = e & 63; kk = e >> 6; } else { kk = e % kGK; c = e / kGK; }
       const int64_t bk = k0 + kk, gj = j0 + c;
       rb[t] = (gj < g.N && bk < ke && b_in_triangle(g, bk, gj)) ? load_opB<TB>(g, bk, gj) : 0.0;
     }
   };
   auto sstore = [&](int buf) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < kGStage; ++t) {
       const int e = tid + 256 * t;
       int r, k;
-      if (g.transA) { k = e & 15; r = e >> 4; } else { r = e & 63; k = e >> 6; }
+      if (g.transA) { k = e % kGK; r = e / kGK; } else { r = e & 63; k = e >> 6; }
       As[buf][as_pos(k, r)] = ra[t];
       int kk, c;
-      if (g.transB) { c = e & 63; kk = e >> 6; } else { kk = e & 15; c = e >> 4; }
+      if (g.transB) { c = e & 63; kk = e >> 6; } else { kk = e % kGK; c = e / kGK; }
       Bs[buf][bs_pos(kk, c)] = rb[t];
     }
   };
@@ -211,30 +215,30 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f32(GemmArgs g) {
   gemm_krange(g, i0, j0, 0, kb, ke);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = (wave & 1) * 32, wc = (wave >> 1) * 32;
-  float ra[4], rb[4];
+  float ra[kGStage], rb[kGStage];
   auto gload = [&](int64_t k0) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < kGStage; ++t) {
       const int e = tid + 256 * t;
       int r, k;
-      if (g.transA) { k = e & 15; r = e >> 4; } else { r = e & 63; k = e >> 6; }
+      if (g.transA) { k = e % kGK; r = e / kGK; } else { r = e & 63; k = e >> 6; }
       const int64_t gi = i0 + r, gk = k0 + k;
       ra[t] = (gi < g.M && gk < ke && a_in_triangle(g, gi, gk)) ? (float)load_opA<double>(g, gi, gk) : 0.0f;
       int kk, c;
-      if (g.transB) { c = e & 63; kk = e >> 6; } else { kk = e & 15; c = e >> 4; }
+      if (g.transB) { c = e & 63; kk = e >> 6; } else { kk = e % kGK; c = e / kGK; }
       const int64_t bk = k0 + kk, gj = j0 + c;
       rb[t] = (gj < g.N && bk < ke && b_in_triangle(g, bk, gj)) ? (float)load_opB<double>(g, bk, gj) : 0.0f;
     }
   };
   auto sstore = [&](int buf) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < kGStage; ++t) {
       const int e = tid + 256 * t;
       int r, k;
-      if (g.transA) { k = e & 15; r = e >> 4; } else { r = e & 63; k = e >> 6; }
+      if (g.transA) { k = e % kGK; r = e / kGK; } else { r = e & 63; k = e >> 6; }
       As[buf][as_pos(k, r)] = ra[t];
       int kk, c;
-      if (g.transB) { c = e & 63; kk = e >> 6; } else { kk = e & 15; c = e >> 4; }
+      if (g.transB) { c = e & 63; kk = e >> 6; } else { kk = e % kGK; c = e / kGK; }
       Bs[buf][bs_pos(kk, c)] = rb[t];
     }
   };
