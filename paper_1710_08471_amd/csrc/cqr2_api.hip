@@ -486,7 +486,7 @@ int cqr2_lstsq(const double* A, int64_t m, int64_t n, int64_t lda, const double*
 size_t cqr2_gram_workspace_size(int64_t m, int64_t n) {
   if (m < 0 || n < 1 || n > CQR2_MAX_N) return 0;
   if (n <= kSmallN) return align_up(cqr2::plan_gram(m, n).partial_bytes);
-  if (n <= cqr2::kWideMaxN) return align_up(cqr2::plan_gram_wide(m).partial_bytes);
+  if (n <= cqr2::kWideMaxN) return align_up(cqr2::plan_gram_wide(m, n).partial_bytes);
   return align_up(cqr2::plan_syrk(m, n).partial_bytes);
 }
 
@@ -515,7 +515,7 @@ int cqr2_gram(const double* A, int64_t m, int64_t n, int64_t lda, double* W, int
     return 0;
   }
   if (n <= cqr2::kWideMaxN) {
-    CQR2_TRY(cqr2::launch_gram_wide(cqr2::plan_gram_wide(m), 0, A, m, (int)n, lda, (double*)work, W, ldw, nullptr,
+    CQR2_TRY(cqr2::launch_gram_wide(cqr2::plan_gram_wide(m, n), 0, A, m, (int)n, lda, (double*)work, W, ldw, nullptr,
                                     s));
     CQR2_TRY(cqr2::launch_mirror_lower(W, ldw, n, s));
     return 0;

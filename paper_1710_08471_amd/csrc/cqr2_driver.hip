@@ -290,7 +290,7 @@ GeneralPlan plan_general(int64_t m, int64_t n, bool mixed, int depth) {
   p.off_p = take(nn);
   p.off_uimg = take(upper_image_bytes(n));
   // the Gram's partials (FP64 or FP32 input alike)
-  const size_t gws = n <= kWideMaxN ? plan_gram_wide(m).partial_bytes : plan_syrk(m, n).partial_bytes;
+  const size_t gws = n <= kWideMaxN ? plan_gram_wide(m, n).partial_bytes : plan_syrk(m, n).partial_bytes;
   const size_t rws = cholinv_rec_workspace(n);
   p.off_scratch = take(gws > rws ? gws : rws);
   p.off_q1 = take((size_t)m * n * (mixed ? sizeof(float) : sizeof(double)));
@@ -344,7 +344,7 @@ hipError_t factor_general(const double* A, int64_t m, int64_t n, int64_t lda, do
   const int q1f = mixed ? 1 : 0;  // element type of the stored Q1
   // n <= 256: tall-skinny kernels (A read once per step); above: tiled GEMMs
   const bool wide = n <= kWideMaxN;
-  const WideGramPlan wp = plan_gram_wide(m);
+  const WideGramPlan wp = plan_gram_wide(m, n);
   const SyrkPlan sp = wide ? SyrkPlan{} : plan_syrk(m, n);
   CQR2_HIP(launch_set_info(info, 0, s));
   // pass 1: CQR(A) -> Q1 (workspace), R1

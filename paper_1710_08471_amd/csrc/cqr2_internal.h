@@ -91,6 +91,9 @@ hipError_t launch_stream16_apply_gram(const Stream16Plan& p, const double* A, in
 // products and sums into an FP32 Q; neither: FP64.  Q may equal A (same type).
 hipError_t launch_apply256(int a_f32, int f32_math, const void* A, int64_t m, int n, int64_t lda,
                            const double* Uimg, void* Q, int64_t ldq, const int32_t* info, hipStream_t s);
+// The same for n <= 128 (Uimg: the 256-wide image; 128-column kernel, four waves).
+hipError_t launch_apply128(int a_f32, int f32_math, const void* A, int64_t m, int n, int64_t lda,
+                           const double* Uimg, void* Q, int64_t ldq, const int32_t* info, hipStream_t s);
 // Fixed-order sum of the partials into the symmetric W (n x n, ldw).
 hipError_t launch_stream16_reduce(const Stream16Plan& p, const double* partials, int n, double* W, int64_t ldw,
                                   const int32_t* info, hipStream_t s);
@@ -128,10 +131,11 @@ hipError_t launch_gemm_f32(int transA, int transB, int64_t M, int64_t N, int64_t
 constexpr int64_t kWideMaxN = 256;
 struct WideGramPlan {
   int64_t stages = 0, stages_per_wg = 0;  // 32-row stages
-  int splits = 0;
+  int splits = 0, ntiles = 0;             // lower 16 x 16 tiles per split
   size_t partial_bytes = 0;
 };
-WideGramPlan plan_gram_wide(int64_t m);
+// n <= 128 takes the 128-column kernel (36 tiles, up to 512 splits).
+WideGramPlan plan_gram_wide(int64_t m, int64_t n);
 // Lower triangle of W = AᵀA (n <= 256); A is FP64, or FP32 when a_f32.
 hipError_t launch_gram_wide(const WideGramPlan& p, int a_f32, const void* A, int64_t m, int n, int64_t lda,
                             double* partials, double* W, int64_t ldw, const int32_t* info, hipStream_t s);

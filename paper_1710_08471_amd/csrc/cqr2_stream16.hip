@@ -775,6 +775,38 @@ __global__ __launch_bounds__(kThreads, 1) void k_apply256(const TA* A, int64_t m
 #undef CQR2_A256
 }
 
+// Q = A U for n <= 128 with the 128-column form of the same body: four waves,
+// several workgroups per CU.  The mixed form's kernels at n <= 128 (FP32
+// arithmetic into an FP32 Q1; FP32 Q1 widened exactly), and FP64 column
+// blocks of the partial inverse.
+template <typename TA, bool F32, int SR, int NBUF>
+__global__ __launch_bounds__(256, 2) void k_apply128(const TA* A, int64_t m, int n, int64_t lda,
+                                                    const double* __restrict__ U, void* Q, int64_t ldq,
+                                                    int64_t stages, int64_t spw, const int32_t* info) {
+  __shared__ __attribute__((aligned(16))) TA smem[NBUF * 128 * SR];
+  if (info != nullptr && *info != 0) return;
+  constexpr int kF = kPlanRows / SR;
+  const int64_t nst = (m + SR - 1) / SR;
+  const int64_t u0 = (int64_t)blockIdx.x * spw;
+  const int64_t u1 = u0 + spw < stages ? u0 + spw : stages;
+  const int64_t s0 = u0 * kF;
+  const int64_t s1 = u1 * kF < nst ? u1 * kF : nst;
+  for (int e = threadIdx.x; e < NBUF * 128 * SR; e += 256)
+    if ((e % (128 * SR)) / SR >= n) smem[e] = (TA)0;
+  const bool direct_ok = (((uintptr_t)A & 15u) == 0) && (((lda * (int64_t)sizeof(TA)) & 15) == 0) &&
+                         lda <= ((int64_t)1 << 26);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+#define CQR2_A128(WV) applyw_body<TA, F32, 128, SR, NBUF, WV>(A, m, n, lda, U, Q, ldq, s0, s1, direct_ok, smem)
+  switch (wave) {
+    case 0: CQR2_A128(0); break;
+    case 1: CQR2_A128(1); break;
+    case 2: CQR2_A128(2); break;
+    case 3: CQR2_A128(3); break;
+    default: break;
+  }
+#undef CQR2_A128
+}
+
 __global__ __launch_bounds__(256) void k_gram16_reduce(const double* __restrict__ part, int splits, int n,
                                                        double* __restrict__ W, int64_t ldw,
                                                        const int32_t* __restrict__ info) {
@@ -830,6 +862,28 @@ hipError_t launch_apply256(int a_f32, int f32_math, const void* A, int64_t m, in
   else
     hipLaunchKernelGGL((k_apply256<double, false, 32, 2>), g, b, 0, s, (const double*)A, m, n, lda, Uimg, Q, ldq,
                        p.stages, p.stages_per_wg, info);
+  return hipGetLastError();
+}
+
+hipError_t launch_apply128(int a_f32, int f32_math, const void* A, int64_t m, int n, int64_t lda,
+                           const double* Uimg, void* Q, int64_t ldq, const int32_t* info, hipStream_t s) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  // 64-row plan units, at least two per workgroup, at most 1024 workgroups
+  const int64_t stages = (m + kPlanRows - 1) / kPlanRows;
+  int64_t wgs = stages / 2;
+  if (wgs < 1) wgs = 1;
+  if (wgs > 1024) wgs = 1024;
+  const int64_t spw = (stages + wgs - 1) / wgs;
+  const dim3 g((unsigned)((stages + spw - 1) / spw)), b(256);
+  if (f32_math)
+    hipLaunchKernelGGL((k_apply128<double, true, 32, 2>), g, b, 0, s, (const double*)A, m, n, lda, Uimg, Q, ldq,
+                       stages, spw, info);
+  else if (a_f32)
+    hipLaunchKernelGGL((k_apply128<float, false, 32, 4>), g, b, 0, s, (const float*)A, m, n, lda, Uimg, Q, ldq,
+                       stages, spw, info);
+  else
+    hipLaunchKernelGGL((k_apply128<double, false, 32, 2>), g, b, 0, s, (const double*)A, m, n, lda, Uimg, Q, ldq,
+                       stages, spw, info);
   return hipGetLastError();
 }
 

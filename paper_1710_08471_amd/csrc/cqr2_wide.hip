@@ -49,15 +49,38 @@ __global__ __launch_bounds__(64 * kWideWaves, 1) void k_gram_wide(const TA* __re
   }
 }
 
+// n <= 128: the same body over 128 columns (36 lower tiles, four waves; two
+// workgroups per CU).  The mixed form's Grams at n <= 128.
+template <typename TA>
+__global__ __launch_bounds__(256, 2) void k_gram128(const TA* __restrict__ A, int64_t m, int n, int64_t lda,
+                                                   int64_t stages, int64_t spw, double* __restrict__ partials,
+                                                   const int32_t* __restrict__ info) {
+  __shared__ __attribute__((aligned(16))) TA lds[2 * 128 * kWideRows];
+  if (info != nullptr && *info != 0) return;
+  const int64_t st0 = (int64_t)blockIdx.x * spw;
+  const int64_t st1 = st0 + spw < stages ? st0 + spw : stages;
+  const bool direct_ok = (((uintptr_t)A & 15u) == 0) && (((lda * (int64_t)sizeof(TA)) & 15) == 0);
+  double* out = partials + (int64_t)blockIdx.x * kLower128 * 256;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  switch (wave) {
+    case 0: gram_cols_wave<TA, 128, 0>(A, m, n, lda, st0, st1, direct_ok, lds, out); break;
+    case 1: gram_cols_wave<TA, 128, 1>(A, m, n, lda, st0, st1, direct_ok, lds, out); break;
+    case 2: gram_cols_wave<TA, 128, 2>(A, m, n, lda, st0, st1, direct_ok, lds, out); break;
+    case 3: gram_cols_wave<TA, 128, 3>(A, m, n, lda, st0, st1, direct_ok, lds, out); break;
+    default: break;
+  }
+}
+
 // Sum of the partials in split order (8 contiguous sub-ranges added in
-// order), written to the lower triangle of W (n x n, ldw).
-__global__ __launch_bounds__(256) void k_gram_wide_reduce(const double* __restrict__ part, int splits, int n,
-                                                          double* __restrict__ W, int64_t ldw,
+// order), written to the lower triangle of W (n x n, ldw); ntiles lower
+// tiles per split (136, or 36 for the 128-column Gram).
+__global__ __launch_bounds__(256) void k_gram_wide_reduce(const double* __restrict__ part, int splits, int ntiles,
+                                                          int n, double* __restrict__ W, int64_t ldw,
                                                           const int32_t* __restrict__ info) {
   __shared__ double red[8][32];
   if (info != nullptr && *info != 0) return;
   const int lanei = threadIdx.x & 31, sub = threadIdx.x >> 5;
-  constexpr int total = kWideLower * 256;
+  const int total = ntiles * 256;
   const int e = blockIdx.x * 32 + lanei;
   double v = 0.0;
   if (e < total) {
@@ -87,32 +110,44 @@ __global__ __launch_bounds__(256) void k_gram_wide_reduce(const double* __restri
   if (row >= col && row < n) W[row + (int64_t)col * ldw] = t;
 }
 
-WideGramPlan plan_gram_wide(int64_t m) {
+WideGramPlan plan_gram_wide(int64_t m, int64_t n) {
   WideGramPlan p{};
+  const bool narrow = n <= 128;  // the 128-column kernel: smaller workgroups, twice as many
+  p.ntiles = narrow ? kLower128 : kWideLower;
   p.stages = m > 0 ? (m + kWideRows - 1) / kWideRows : 1;
   int64_t s = p.stages / 4;  // at least 4 stages per workgroup
   if (s < 1) s = 1;
-  if (s > kWideSplits) s = kWideSplits;
+  const int64_t cap = narrow ? 2 * kWideSplits : kWideSplits;
+  if (s > cap) s = cap;
   p.stages_per_wg = (p.stages + s - 1) / s;
   p.splits = (int)((p.stages + p.stages_per_wg - 1) / p.stages_per_wg);
-  p.partial_bytes = (size_t)p.splits * kWideLower * 256 * sizeof(double);
+  p.partial_bytes = (size_t)p.splits * p.ntiles * 256 * sizeof(double);
   return p;
 }
 
 hipError_t launch_gram_wide(const WideGramPlan& p, int a_f32, const void* A, int64_t m, int n, int64_t lda,
                             double* partials, double* W, int64_t ldw, const int32_t* info, hipStream_t s) {
   if (n > kWideCols) return hipErrorInvalidValue;
-  if (a_f32)
+  if (p.ntiles == kLower128 && n > 128) return hipErrorInvalidValue;
+  if (p.ntiles == kLower128) {
+    if (a_f32)
+      hipLaunchKernelGGL(k_gram128<float>, dim3(p.splits), dim3(256), 0, s, (const float*)A, m, n, lda, p.stages,
+                         p.stages_per_wg, partials, info);
+    else
+      hipLaunchKernelGGL(k_gram128<double>, dim3(p.splits), dim3(256), 0, s, (const double*)A, m, n, lda, p.stages,
+                         p.stages_per_wg, partials, info);
+  } else if (a_f32) {
     hipLaunchKernelGGL(k_gram_wide<float>, dim3(p.splits), dim3(64 * kWideWaves), 0, s, (const float*)A, m, n, lda,
                        p.stages, p.stages_per_wg, partials, info);
-  else
+  } else {
     hipLaunchKernelGGL(k_gram_wide<double>, dim3(p.splits), dim3(64 * kWideWaves), 0, s, (const double*)A, m, n,
                        lda, p.stages, p.stages_per_wg, partials, info);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int total = kWideLower * 256;
-  hipLaunchKernelGGL(k_gram_wide_reduce, dim3((total + 31) / 32), dim3(256), 0, s, partials, p.splits, n, W, ldw,
-                     info);
+  const int total = p.ntiles * 256;
+  hipLaunchKernelGGL(k_gram_wide_reduce, dim3((total + 31) / 32), dim3(256), 0, s, partials, p.splits, p.ntiles, n,
+                     W, ldw, info);
   return hipGetLastError();
 }
 
@@ -586,8 +621,9 @@ hipError_t launch_upper_image(const double* X, int64_t ldx, int n, double* T, hi
 hipError_t launch_tall_gemm(int a_f32, const void* A, int64_t m, int n, int64_t lda, const double* Uimg, double* Q,
                             int64_t ldq, const int32_t* info, hipStream_t s) {
   if (m <= 0 || n <= 0) return hipSuccess;
-  // 128 < n <= 256: the MFMA 16x16x4 streaming kernel
-  if (n > 128 && n <= kTallUld) return launch_apply256(a_f32, 0, A, m, n, lda, Uimg, Q, ldq, info, s);
+  // n <= 256: the MFMA 16x16x4 streaming kernels (128 or 256 columns)
+  if (n <= 128) return launch_apply128(a_f32, 0, A, m, n, lda, Uimg, Q, ldq, info, s);
+  if (n <= kTallUld) return launch_apply256(a_f32, 0, A, m, n, lda, Uimg, Q, ldq, info, s);
   const int64_t ld = upper_image_ld(n);
   dim3 grid((unsigned)((m + kTallRows - 1) / kTallRows), (unsigned)(ld / kTallUld));
   if (a_f32)
@@ -602,7 +638,8 @@ hipError_t launch_tall_gemm(int a_f32, const void* A, int64_t m, int n, int64_t 
 hipError_t launch_tall_gemm_f32(const double* A, int64_t m, int n, int64_t lda, const double* Uimg, float* Q,
                                 int64_t ldq, const int32_t* info, hipStream_t s) {
   if (m <= 0 || n <= 0) return hipSuccess;
-  if (n > 128 && n <= kTallUld) return launch_apply256(0, 1, A, m, n, lda, Uimg, Q, ldq, info, s);
+  if (n <= 128) return launch_apply128(0, 1, A, m, n, lda, Uimg, Q, ldq, info, s);
+  if (n <= kTallUld) return launch_apply256(0, 1, A, m, n, lda, Uimg, Q, ldq, info, s);
   const int64_t ld = upper_image_ld(n);
   dim3 grid((unsigned)((m + kTallRows - 1) / kTallRows), (unsigned)(ld / kTallUld));
   hipLaunchKernelGGL((k_tall<double, true>), grid, dim3(512), 0, s, A, m, n, lda, Uimg, ld, (void*)Q, ldq, info);

@@ -24,13 +24,11 @@ __device__ __forceinline__ int spos(int c, int r) {
   return c * SR + (r ^ ((c & 15) << 1));
 }
 
-constexpr int kA256Waves = 8;
-constexpr int kA256Threads = 64 * kA256Waves;
-
-// ---- Q = A U for 128 < n <= 256 ----------------------------------------------
-// U as its zero-padded row-major image (ld 256).  Eight waves; wave w owns the
-// output column tiles w and 15 - w (68 k-steps of 4 per 16-row tile in all,
-// the same for every wave) with their U fragments in registers, and both
+// ---- Q = A U for 64 < n <= 256 -----------------------------------------------
+// U as its zero-padded row-major image (ld 256).  COLS = 256 (eight waves) or
+// 128 (four waves); wave w owns the output column tiles w and COLS/16 - 1 - w
+// (at COLS = 256, 68 k-steps of 4 per 16-row tile in all, the same for every
+// wave) with their U fragments in registers, and both
 // 16-row tiles of each 32-row stage: one read gives lane l A(2 (l%16),
 // 4t + l/16) and the row below, the even-row and the odd-row tile.  Products
 // on Qᵀ = Uᵀ Aᵀ, so a store covers 4 columns x 16 alternate rows (the other
@@ -41,8 +39,7 @@ constexpr int kA256Threads = 64 * kA256Waves;
 //        fl32(A) and fl32(U), into an FP32 Q (the mixed form's pass 1).
 // Result layouts: FP64 16x16x4 entry r of lane l is D(4r + l/16, l%16);
 // FP32 16x16x4 entry r is D(4 (l/16) + r, l%16).
-constexpr int kWCols = 256;
-constexpr int kWTiles = kWCols / 16;
+constexpr int kWCols = 256;  // leading dimension of the U image; the widest stage
 
 template <typename TA, int SR>
 __device__ __forceinline__ int wpos(int c, int r) {
@@ -50,19 +47,22 @@ __device__ __forceinline__ int wpos(int c, int r) {
   else return c * SR + r;  // a fragment read takes 16 lanes x 8 contiguous bytes of one column
 }
 
-template <typename TA, bool F32, int SR, int NBUF, int W>
-__device__ __forceinline__ void apply256_body(const TA* A, int64_t m, int n, int64_t lda,
-                                              const double* __restrict__ U, void* Qv, int64_t ldq, int64_t s_begin,
-                                              int64_t s_end, bool direct_ok, TA* smem) {
+template <typename TA, bool F32, int COLS, int SR, int NBUF, int W>
+__device__ __forceinline__ void applyw_body(const TA* A, int64_t m, int n, int64_t lda,
+                                            const double* __restrict__ U, void* Qv, int64_t ldq, int64_t s_begin,
+                                            int64_t s_end, bool direct_ok, TA* smem) {
   static_assert(SR == 32, "two interleaved 16-row tiles per stage");
   static_assert(!F32 || sizeof(TA) == 8, "FP32 arithmetic takes the FP64 A");
+  static_assert(COLS == 128 || COLS == 256, "128 or 256 columns");
   using UT = typename std::conditional<F32, float, double>::type;
-  constexpr int kBuf = kWCols * SR;            // elements of TA per stage
+  constexpr int kWaves = COLS / 32;
+  constexpr int kThreads = 64 * kWaves;
+  constexpr int kBuf = COLS * SR;              // elements of TA per stage
   constexpr int kRowsPerLane = 16 / (int)sizeof(TA);  // rows per 16-byte copy
   constexpr int kLPC = SR / kRowsPerLane;
   constexpr int kCPI = 64 / kLPC;
-  constexpr int kInstr = kWCols / kCPI;
-  constexpr int J0 = W, J1 = kWTiles - 1 - W;
+  constexpr int kInstr = COLS / kCPI;
+  constexpr int J0 = W, J1 = COLS / 16 - 1 - W;
   constexpr int K0 = 4 * (J0 + 1), K1 = 4 * (J1 + 1);
   const int tid = threadIdx.x, lane = tid & 63;
   const int64_t count = s_end - s_begin;
@@ -77,13 +77,13 @@ __device__ __forceinline__ void apply256_body(const TA* A, int64_t m, int n, int
   }
   int fcount = 0;
 #pragma unroll
-  for (int p = W; p < kInstr; p += kA256Waves) fcount += (kCPI * p < n) ? 1 : 0;
+  for (int p = W; p < kInstr; p += kWaves) fcount += (kCPI * p < n) ? 1 : 0;
   auto fill = [&](int64_t st, TA* buf) {
     const int64_t row0 = st * SR;
     if (direct_ok && row0 + SR <= m) {
       const int sub = lane / kLPC, lrow = kRowsPerLane * (lane % kLPC);
 #pragma unroll
-      for (int p = W; p < kInstr; p += kA256Waves) {
+      for (int p = W; p < kInstr; p += kWaves) {
         if (kCPI * p < n) {
           const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
               (void*)(A + row0 + (int64_t)(kCPI * p) * lda), 0, 0x7fffffff, kBufferRsrcWord3);
@@ -97,7 +97,7 @@ __device__ __forceinline__ void apply256_body(const TA* A, int64_t m, int n, int
         }
       }
     } else {
-      for (int e = tid; e < kBuf; e += kA256Threads) {
+      for (int e = tid; e < kBuf; e += kThreads) {
         const int c = e / SR, r = e % SR;
         const int64_t row = row0 + r;
         if (c < n) buf[wpos<TA, SR>(c, r)] = row < m ? A[row + (int64_t)c * lda] : (TA)0;
@@ -135,21 +135,30 @@ __device__ __forceinline__ void apply256_body(const TA* A, int64_t m, int n, int
     double2 a[3];
     a[0] = afrag(0);
     a[1] = afrag(1);
+    // at COLS = 128 the k-steps past n (zero columns of A) and a tile past n
+    // are skipped (uniform branches); at COLS = 256 both tests fold away
+    const bool on1 = COLS == 256 || 16 * J1 < n;
 #pragma unroll
     for (int t = 0; t < K1; ++t) {
       if (t + 2 < K1) a[(t + 2) % 3] = afrag(t + 2);
       __builtin_amdgcn_sched_barrier(0);
-      if constexpr (F32) {
+      const bool kon = COLS == 256 || 4 * t < n;
+      if (!kon) {
+      } else if constexpr (F32) {
         const float ax = (float)a[t % 3].x, ay = (float)a[t % 3].y;
-        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(u1[t], ax, acc[0][1], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(u1[t], ay, acc[1][1], 0, 0, 0);
+        if (on1) {
+          acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(u1[t], ax, acc[0][1], 0, 0, 0);
+          acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(u1[t], ay, acc[1][1], 0, 0, 0);
+        }
         if (t < K0) {
           acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(u0[t], ax, acc[0][0], 0, 0, 0);
           acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(u0[t], ay, acc[1][0], 0, 0, 0);
         }
       } else {
-        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(u1[t], a[t % 3].x, acc[0][1], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(u1[t], a[t % 3].y, acc[1][1], 0, 0, 0);
+        if (on1) {
+          acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(u1[t], a[t % 3].x, acc[0][1], 0, 0, 0);
+          acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(u1[t], a[t % 3].y, acc[1][1], 0, 0, 0);
+        }
         if (t < K0) {
           acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(u0[t], a[t % 3].x, acc[0][0], 0, 0, 0);
           acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(u0[t], a[t % 3].y, acc[1][0], 0, 0, 0);
@@ -182,6 +191,14 @@ __device__ __forceinline__ void apply256_body(const TA* A, int64_t m, int n, int
     for (int h = NBUF - 2; h > 0; --h) shist[h] = shist[h - 1];
     shist[0] = issued;
   }
+}
+
+
+template <typename TA, bool F32, int SR, int NBUF, int W>
+__device__ __forceinline__ void apply256_body(const TA* A, int64_t m, int n, int64_t lda,
+                                              const double* __restrict__ U, void* Qv, int64_t ldq, int64_t s_begin,
+                                              int64_t s_end, bool direct_ok, TA* smem) {
+  applyw_body<TA, F32, 256, SR, NBUF, W>(A, m, n, lda, U, Qv, ldq, s_begin, s_end, direct_ok, smem);
 }
 
 }  // namespace cqr2

@@ -28,6 +28,7 @@ constexpr int kWideRows = 32;
 constexpr int kWideCols = 256;
 constexpr int kWideTiles = kWideCols / 16;                        // 16
 constexpr int kWideLower = kWideTiles * (kWideTiles + 1) / 2;     // 136
+constexpr int kLower128 = 8 * 9 / 2;                                // 36: the 128-column Gram
 constexpr int kWideWaves = 8;
 constexpr int kWideBuf = kWideCols * kWideRows;                   // doubles per stage
 constexpr int kWideSplits = 256;
@@ -45,34 +46,38 @@ __device__ __forceinline__ int wide_slot(int c, int r) {
 
 typedef double wd4 __attribute__((ext_vector_type(4)));
 
-template <int W>
+// COLS = 256 (eight waves) or 128 (four waves, tile rows w and 7 - w).
+template <int COLS, int W>
 struct WideWave {
-  static constexpr int I0 = W, I1 = kWideTiles - 1 - W;
+  static constexpr int I0 = W, I1 = COLS / 16 - 1 - W;
   static constexpr int NT = (I0 + 1) + (I1 + 1);   // tiles of this wave
   static constexpr int NF = I1 + 1;                 // fragments needed (columns tiles 0..I1)
   static constexpr int tile_i(int t) { return t <= I0 ? I0 : I1; }
   static constexpr int tile_j(int t) { return t <= I0 ? t : t - (I0 + 1); }
 };
 
-template <typename TA, int W>
-__device__ __forceinline__ void gram_wide_wave(const TA* __restrict__ A, int64_t m, int n, int64_t lda,
+template <typename TA, int COLS, int W>
+__device__ __forceinline__ void gram_cols_wave(const TA* __restrict__ A, int64_t m, int n, int64_t lda,
                                                int64_t st0, int64_t st1, bool direct_ok, TA* lds,
                                                double* __restrict__ out) {
-  using WW = WideWave<W>;
+  static_assert(COLS == 128 || COLS == 256, "128 or 256 columns");
+  constexpr int kWaves = COLS / 32;
+  constexpr int kBuf = COLS * kWideRows;  // elements per stage
+  using WW = WideWave<COLS, W>;
   const int tid = threadIdx.x, lane = tid & 63;
   wd4 acc[WW::NT];
 #pragma unroll
   for (int t = 0; t < WW::NT; ++t) acc[t] = wd4{0.0, 0.0, 0.0, 0.0};
 
-  for (int e = tid; e < 2 * kWideBuf; e += 64 * kWideWaves)
-    if ((e % kWideBuf) / kWideRows >= n) lds[e] = (TA)0;
+  for (int e = tid; e < 2 * kBuf; e += 64 * kWaves)
+    if ((e % kBuf) / kWideRows >= n) lds[e] = (TA)0;
   auto fill = [&](int64_t st, TA* buf) {
     const int64_t row0 = st * kWideRows;
     if (direct_ok && row0 + kWideRows <= m) {
       if constexpr (sizeof(TA) == 8) {
         // one instruction: 4 columns x 32 rows; lane i -> column 4p + (i>>4), LDS rows 2(i&15), +1
         const int sub = lane >> 4, lrow = 2 * (lane & 15);
-        for (int p = W; p < kWideCols / 4; p += kWideWaves) {
+        for (int p = W; p < COLS / 4; p += kWaves) {
           const int col = 4 * p + sub;
           if (col < n) {
             const int grow = lrow ^ ((col & 15) << 1);
@@ -84,7 +89,7 @@ __device__ __forceinline__ void gram_wide_wave(const TA* __restrict__ A, int64_t
       } else {
         // one instruction: 8 columns x 32 rows; lane i -> column 8p + (i>>3), LDS rows 4(i&7) .. +3
         const int sub = lane >> 3, lrow = 4 * (lane & 7);
-        for (int p = W; p < kWideCols / 8; p += kWideWaves) {
+        for (int p = W; p < COLS / 8; p += kWaves) {
           const int col = 8 * p + sub;
           if (col < n) {
             const int grow = lrow ^ (((col >> 1) & 7) << 2);
@@ -95,7 +100,7 @@ __device__ __forceinline__ void gram_wide_wave(const TA* __restrict__ A, int64_t
         }
       }
     } else {
-      for (int e = tid; e < kWideBuf; e += 64 * kWideWaves) {
+      for (int e = tid; e < kBuf; e += 64 * kWaves) {
         const int c = e / kWideRows, r = e % kWideRows;
         const int64_t row = row0 + r;
         buf[wide_slot<TA>(c, r)] = (row < m && c < n) ? A[row + (int64_t)c * lda] : (TA)0;
@@ -109,8 +114,8 @@ __device__ __forceinline__ void gram_wide_wave(const TA* __restrict__ A, int64_t
   const int fc = lane & 15, fk = lane >> 4;
   for (int64_t st = st0; st < st1; ++st) {
     const int cur = (int)((st - st0) & 1);
-    TA* bcur = lds + cur * kWideBuf;
-    if (st + 1 < st1) fill(st + 1, lds + (cur ^ 1) * kWideBuf);
+    TA* bcur = lds + cur * kBuf;
+    if (st + 1 < st1) fill(st + 1, lds + (cur ^ 1) * kBuf);
 #pragma unroll 1
     for (int k0 = 0; k0 < kWideRows; k0 += 4) {
       double f[WW::NF];
@@ -132,6 +137,13 @@ __device__ __forceinline__ void gram_wide_wave(const TA* __restrict__ A, int64_t
 #pragma unroll
     for (int r = 0; r < 4; ++r) o[r * 64 + lane] = acc[t][r];
   }
+}
+
+template <typename TA, int W>
+__device__ __forceinline__ void gram_wide_wave(const TA* __restrict__ A, int64_t m, int n, int64_t lda,
+                                               int64_t st0, int64_t st1, bool direct_ok, TA* lds,
+                                               double* __restrict__ out) {
+  gram_cols_wave<TA, 256, W>(A, m, n, lda, st0, st1, direct_ok, lds, out);
 }
 
 }  // namespace cqr2
