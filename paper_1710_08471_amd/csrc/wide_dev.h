@@ -111,20 +111,33 @@ __device__ __forceinline__ void gram_cols_wave(const TA* __restrict__ A, int64_t
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
 
-  const int fc = lane & 15, fk = lane >> 4;
   for (int64_t st = st0; st < st1; ++st) {
     const int cur = (int)((st - st0) & 1);
     TA* bcur = lds + cur * kBuf;
     if (st + 1 < st1) fill(st + 1, lds + (cur ^ 1) * kBuf);
-#pragma unroll 1
-    for (int k0 = 0; k0 < kWideRows; k0 += 4) {
-      double f[WW::NF];
+    // lane index behind an opaque copy, so the fragment addresses are formed
+    // here and not hoisted out of the stage loop into registers
+    int ln = lane;
+    asm volatile("" : "+v"(ln));
+    const int fc = ln & 15, fk = ln >> 4;
+    // the fragments of k-step ks + 1 are read while the products of k-step ks run
+    double f[2][WW::NF];
 #pragma unroll
-      for (int c = 0; c < WW::NF; ++c) f[c] = (double)bcur[wide_slot<TA>(16 * c + fc, k0 + fk)];
+    for (int c = 0; c < WW::NF; ++c) f[0][c] = (double)bcur[wide_slot<TA>(16 * c + fc, fk)];
+#pragma unroll
+    for (int ks = 0; ks < kWideRows / 4; ++ks) {
+      if (ks + 1 < kWideRows / 4) {
+#pragma unroll
+        for (int c = 0; c < WW::NF; ++c)
+          f[(ks + 1) & 1][c] = (double)bcur[wide_slot<TA>(16 * c + fc, 4 * (ks + 1) + fk)];
+      }
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int t = 0; t < WW::NT; ++t)
         if (16 * WW::tile_i(t) < n)  // uniform: tiles past column n stay zero
-          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(f[WW::tile_i(t)], f[WW::tile_j(t)], acc[t], 0, 0, 0);
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(f[ks & 1][WW::tile_i(t)], f[ks & 1][WW::tile_j(t)], acc[t], 0,
+                                                        0, 0);
+      __builtin_amdgcn_sched_barrier(0);
     }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
