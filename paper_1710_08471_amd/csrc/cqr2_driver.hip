@@ -78,8 +78,20 @@ static hipError_t zero_block(double* X, int64_t ldx, int64_t rows, int64_t cols,
 // W: n x n (ldw), lower triangle read; its trailing blocks are overwritten by
 // Schur complements.  R, Rinv: n x n upper (ldr, ldri), strictly lower parts 0.
 // work: >= cholinv_rec_workspace(n) bytes.
-hipError_t cholinv_recursive(double* W, int64_t ldw, int64_t n, double* R, int64_t ldr, double* Rinv, int64_t ldri,
-                             char* work, int32_t* info, int info_offset, hipStream_t s, int depth) {
+// Zeros below the diagonal of R and Rinv (n x n), in one launch.
+__global__ void k_zero_lower2(double* R, int64_t ldr, double* Rinv, int64_t ldri, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * n) return;
+  const int64_t i = e % n, j = e / n;
+  if (i <= j) return;
+  R[i + j * ldr] = 0.0;
+  Rinv[i + j * ldri] = 0.0;
+}
+
+// The recursion proper: the strictly lower blocks off the diagonal are left
+// for the caller (cholinv_recursive zeroes them all in one launch).
+static hipError_t cholinv_rec(double* W, int64_t ldw, int64_t n, double* R, int64_t ldr, double* Rinv, int64_t ldri,
+                              char* work, int32_t* info, int info_offset, hipStream_t s, int depth) {
   if (n <= kBaseN) return launch_cholinv(W, ldw, (int)n, R, ldr, Rinv, ldri, nullptr, 0, info, info_offset, s);
   const int64_t h = cholinv_split(n), n2 = n - h;
   double* W22 = W + h + h * ldw;
@@ -91,7 +103,7 @@ hipError_t cholinv_recursive(double* W, int64_t ldw, int64_t n, double* R, int64
   double* gws = (double*)(work + (size_t)h * n2 * sizeof(double));
   const int sub = depth > 0 ? depth - 1 : 0;
   // leading diagonal block: its factor and inverse, recursively
-  CQR2_HIP(cholinv_recursive(W, ldw, h, R, ldr, Rinv, ldri, work, info, info_offset, s, sub));
+  CQR2_HIP(cholinv_rec(W, ldw, h, R, ldr, Rinv, ldri, work, info, info_offset, s, sub));
   if (depth == 0) {
     // off-diagonal block of the factor from the leading inverse, kept transposed
     // in R's upper part: R12 = Rinv11ᵀ A21ᵀ
@@ -119,7 +131,7 @@ hipError_t cholinv_recursive(double* W, int64_t ldw, int64_t n, double* R, int64
   CQR2_HIP(launch_gemm(1, 0, n2, n2, h, -1.0, R12, ldr, R12, ldr, 1.0, W22, ldw, GEMM_C_LOWER,
                        rec_splits(n2, n2, h), gws, info, s));
   // trailing diagonal block: factor and inverse of the Schur complement
-  CQR2_HIP(cholinv_recursive(W22, ldw, n2, R22, ldr, Ri22, ldri, work, info, info_offset + (int)h, s, sub));
+  CQR2_HIP(cholinv_rec(W22, ldw, n2, R22, ldr, Ri22, ldri, work, info, info_offset + (int)h, s, sub));
   if (depth == 0) {
     // off-diagonal block of the inverse from the two diagonal inverses and
     // R12: Rinv12 = -(Rinv11 R12) Rinv22
@@ -130,10 +142,16 @@ hipError_t cholinv_recursive(double* W, int64_t ldw, int64_t n, double* R, int64
   } else {
     CQR2_HIP(zero_block(Ri12, ldri, h, n2, s));  // the inverse's off-diagonal block is not formed at this level
   }
-  // strictly lower blocks of the triangular factors
-  CQR2_HIP(zero_block(R + h, ldr, n2, h, s));
-  CQR2_HIP(zero_block(Rinv + h, ldri, n2, h, s));
   return hipSuccess;
+}
+
+hipError_t cholinv_recursive(double* W, int64_t ldw, int64_t n, double* R, int64_t ldr, double* Rinv, int64_t ldri,
+                             char* work, int32_t* info, int info_offset, hipStream_t s, int depth) {
+  CQR2_HIP(cholinv_rec(W, ldw, n, R, ldr, Rinv, ldri, work, info, info_offset, s, depth));
+  if (n <= kBaseN) return hipSuccess;  // the one-workgroup kernel zeroes its own lower part
+  const int64_t total = n * n;
+  hipLaunchKernelGGL(k_zero_lower2, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, R, ldr, Rinv, ldri, n);
+  return hipGetLastError();
 }
 
 // After a breakdown (*info != 0): the upper triangle of X (n x n) := NaN.
