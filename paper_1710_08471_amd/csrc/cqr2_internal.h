@@ -223,11 +223,13 @@ hipError_t launch_shift_diag(double* W, int64_t ldw, int64_t n, int64_t m, const
 // Workgroups are dealt to the problems by the table (task t owns workgroups
 // [wg0, wg0 + nwg)); tasks are sorted by wg0.
 constexpr int kStepThreads = 512;
-constexpr int kStepStages = 64;  // 64-row stages per Gram / Q workgroup (4096 rows)
+constexpr int kStepStages = 64;     // 64-row stages per Gram / Q workgroup, at most (4096 rows)
+constexpr int kStepMinStages = 16;  // ... and at least (1024 rows)
 constexpr int kStepPhases = 6;
 constexpr int kStepMaxN = 256;
 constexpr int kStepWidePhases = 8;
-constexpr int kStepWideStages = 64;  // 32-row stages per wide Gram / Q workgroup (2048 rows)
+constexpr int kStepWideStages = 64;     // 32-row stages per wide Gram / Q workgroup, at most (2048 rows)
+constexpr int kStepWideMinStages = 16;  // ... and at least (512 rows)
 struct StepTask {
   const double* A;
   int64_t lda;
@@ -255,9 +257,9 @@ StepLayout step_layout(int64_t m, int64_t n);
 int step_phases(int64_t n);
 // Workgroups of phase `phase` for an m x n problem.
 int step_workgroups(int64_t m, int64_t n, int phase);
-// Rough duration of one workgroup of phase `phase` (microseconds, full row
-// chunk, measured on MI355X); only the order of these values is used.
-double step_wg_cost(int64_t n, int phase);
+// Rough duration of one workgroup of phase `phase` of an m x n problem
+// (microseconds, measured on MI355X); only the order of these values is used.
+double step_wg_cost(int64_t m, int64_t n, int phase);
 hipError_t launch_step(const StepTask* d_tasks, int ntasks, int total_wgs, hipStream_t s);
 
 // ---- least squares on a finished factorization ---------------------------

@@ -314,7 +314,8 @@ struct cqr2_server {
     order.resize(active.size());
     for (size_t i = 0; i < active.size(); ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
-      return cqr2::step_wg_cost(active[x].r.p.n, active[x].phase) > cqr2::step_wg_cost(active[y].r.p.n, active[y].phase);
+      return cqr2::step_wg_cost(active[x].r.p.m, active[x].r.p.n, active[x].phase) >
+             cqr2::step_wg_cost(active[y].r.p.m, active[y].r.p.n, active[y].phase);
     });
     table.clear();
     int wg = 0;

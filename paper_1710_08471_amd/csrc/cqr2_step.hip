@@ -35,9 +35,20 @@ constexpr int kWL = 256;                                       // leading dimens
 constexpr size_t kWideBlock = (size_t)kWL * kWL * sizeof(double);
 enum { WB_W = 0, WB_R1, WB_R2, WB_RI, WB_U1, WB_U2, WB_T, WB_COUNT };
 
+// 32-row stages per wide Gram / Q workgroup: about 64 workgroups per problem,
+// each between 512 and 2048 rows (short workgroups pack a launch better; the
+// lower bound keeps the partial Grams well below A's bytes)
+__host__ __device__ inline int64_t wide_stages_per_chunk(int64_t m) {
+  const int64_t stages = m > 0 ? (m + kWideRows - 1) / kWideRows : 1;
+  int64_t spc = (stages + 63) / 64;
+  if (spc < kStepWideMinStages) spc = kStepWideMinStages;
+  if (spc > kStepWideStages) spc = kStepWideStages;
+  return spc;
+}
 __host__ __device__ inline int wide_chunks(int64_t m) {
   const int64_t stages = m > 0 ? (m + kWideRows - 1) / kWideRows : 1;
-  return (int)((stages + kStepWideStages - 1) / kStepWideStages);
+  const int64_t spc = wide_stages_per_chunk(m);
+  return (int)((stages + spc - 1) / spc);
 }
 // workgroups of the sum phase: about one per split (every entry reads one
 // value per split), at most one entry per thread
@@ -45,6 +56,22 @@ __host__ __device__ inline int wide_reduce_wgs(int64_t m) {
   const int s = wide_chunks(m) + 3;
   return s < kWideRedWGs ? s : kWideRedWGs;
 }
+// n <= 128: 64-row stages per Gram / Q workgroup, about 32 workgroups per
+// problem, each between 1024 and 4096 rows (the CholInv phase sums the
+// partials in one workgroup, so their number stays small)
+__host__ __device__ inline int64_t narrow_stages_per_chunk(int64_t m) {
+  const int64_t stages = m > 0 ? (m + 63) / 64 : 1;
+  int64_t spc = (stages + 31) / 32;
+  if (spc < kStepMinStages) spc = kStepMinStages;
+  if (spc > kStepStages) spc = kStepStages;
+  return spc;
+}
+__host__ __device__ inline int narrow_chunks(int64_t m) {
+  const int64_t stages = m > 0 ? (m + 63) / 64 : 1;
+  const int64_t spc = narrow_stages_per_chunk(m);
+  return (int)((stages + spc - 1) / spc);
+}
+
 // info word (256 bytes), the partial Grams, then the 256 x 256 blocks
 __host__ __device__ inline size_t wide_off(int64_t m, int block) {
   return 256 + (size_t)wide_chunks(m) * kWideLower * 256 * sizeof(double) + (size_t)block * kWideBlock;
@@ -71,7 +98,7 @@ StepLayout step_layout(int64_t m, int64_t n) {
   L.ng = L.np / 4;
   L.nblk = L.ng * (L.ng + 1) / 2;
   const int64_t stages = m > 0 ? (m + 63) / 64 : 1;
-  L.splits = (int)((stages + kStepStages - 1) / kStepStages);
+  L.splits = narrow_chunks(m);
   size_t off = 0;
   L.off_info = off; off += align256(16);
   L.off_part = off; off += align256((size_t)L.splits * L.nblk * 16 * sizeof(double));
@@ -83,20 +110,23 @@ StepLayout step_layout(int64_t m, int64_t n) {
   return L;
 }
 
-double step_wg_cost(int64_t n, int phase) {
+double step_wg_cost(int64_t m, int64_t n, int phase) {
   if (n > 128) {
+    const double rows = (double)(m < wide_stages_per_chunk(m) * kWideRows ? m : wide_stages_per_chunk(m) * kWideRows);
     switch (phase) {
-      case 0: case 4: return 680.0;   // Gram over 2048 rows
-      case 3: case 7: return 820.0;   // Q = A U over 2048 rows
-      case 2: case 6: return 350.0;   // CholInv
-      default: return 20.0;           // sum of the partials
+      case 0: case 4: return 0.33 * rows;   // Gram: 680 us per 2048 rows
+      case 3: case 7: return 0.40 * rows;   // Q = A U: 820 us per 2048 rows
+      case 2: case 6: return 350.0;         // CholInv
+      default: return 20.0;                 // sum of the partials
     }
   }
+  const int64_t crow = narrow_stages_per_chunk(m) * 64;
+  const double f = (double)(m < crow ? (m > 0 ? m : 1) : crow) / 4096.0;  // rows of a chunk / 4096
   const double x = (double)(n < 16 ? 16 : n) - 16.0;
   switch (phase) {
-    case 0: case 3: return 60.0 + 2.8 * x;    // Gram over 4096 rows
-    case 2: case 5: return 140.0 + 3.6 * x;   // Q = A U over 4096 rows
-    default: return 12.0 + 1.2 * x;           // CholInv
+    case 0: case 3: return (60.0 + 2.8 * x) * f;    // Gram over 4096 rows
+    case 2: case 5: return (140.0 + 3.6 * x) * f;   // Q = A U over 4096 rows
+    default: return 12.0 + 1.2 * x;                 // CholInv
   }
 }
 
@@ -114,7 +144,7 @@ int step_workgroups(int64_t m, int64_t n, int phase) {
     }
   }
   const int64_t stages = m > 0 ? (m + 63) / 64 : 1;
-  const int chunks = (int)((stages + kStepStages - 1) / kStepStages);
+  const int chunks = narrow_chunks(m);
   switch (phase) {
     case 0: case 2: case 3: return chunks;
     case 1: case 4: return 1;
@@ -386,8 +416,9 @@ __device__ __forceinline__ void step_run_wide(const StepTask& t, int sub, double
   double* T = (double*)(t.ws + wide_off(m, WB_T));
   const int splits = wide_chunks(m);
   const int64_t nst = m > 0 ? (m + kWideRows - 1) / kWideRows : 0;
-  const int64_t s0 = (int64_t)sub * kStepWideStages;
-  const int64_t s1 = s0 + kStepWideStages < nst ? s0 + kStepWideStages : nst;
+  const int64_t spc = wide_stages_per_chunk(m);
+  const int64_t s0 = (int64_t)sub * spc;
+  const int64_t s1 = s0 + spc < nst ? s0 + spc : nst;
   double* out = part + (int64_t)sub * kWideLower * 256;
   switch (t.phase) {
     case 0:  // Gram of A; the first workgroup resets the info word
@@ -432,9 +463,10 @@ __device__ __forceinline__ void step_run(const StepTask& t, int sub, double* lds
   const int n = t.n;
   const int64_t m = t.m;
   const int64_t stages = m > 0 ? (m + 63) / 64 : 1;
-  const int splits = (int)((stages + kStepStages - 1) / kStepStages);
-  const int64_t s0 = (int64_t)sub * kStepStages;
-  const int64_t s1 = s0 + kStepStages < stages ? s0 + kStepStages : stages;
+  const int splits = narrow_chunks(m);
+  const int64_t spc = narrow_stages_per_chunk(m);
+  const int64_t s0 = (int64_t)sub * spc;
+  const int64_t s1 = s0 + spc < stages ? s0 + spc : stages;
   // workspace (same offsets as step_layout)
   const size_t part_off = 256;
   const size_t part_bytes = ((size_t)splits * NBLK * 16 * sizeof(double) + 255) / 256 * 256;
