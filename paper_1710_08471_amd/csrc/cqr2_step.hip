@@ -6,10 +6,11 @@
 //
 // Each workgroup looks up its task by binary search over the table and runs
 // the same device code as the one-problem kernels.  n <= 128: a Gram partial
-// over up to 4096 rows, CholInv with the partial Grams summed (in split
-// order) as it loads, or Q = A U over up to 4096 rows; the last phase adds one
+// over a chunk of 1024-4096 rows, CholInv with the partial Grams summed (in
+// split order) as it loads, or Q = A U over a chunk; the last phase adds one
 // workgroup that forms R = R2 R1 and publishes the info word.  128 < n <= 256:
-// the same steps with the wide Gram and Q bodies over 2048 rows, a phase that
+// the same steps with the wide Gram and Q bodies over chunks of 512-2048
+// rows, a phase that
 // sums the partial Grams, and a one-workgroup CholInv that splits W once at
 // 128 (Algorithm 2's recursion, first level) and forms the coupling blocks
 // with in-workgroup MFMA products.
