@@ -105,15 +105,51 @@ __device__ __forceinline__ void cholinv_body(const CholInvSrc& src, int n, doubl
   if (info != nullptr && *info != 0) fail = -1;  // an earlier phase failed: skip, NaN outputs
 
   double M[T][T];
+  if (src.part == nullptr) {
 #pragma unroll
-  for (int a = 0; a < T; ++a)
+    for (int a = 0; a < T; ++a)
 #pragma unroll
-    for (int b = 0; b < T; ++b) {
-      const int p = r + G * a, q = c + G * b;
-      double v = 0.0;
-      if (worker && p >= q) v = (p < n) ? cholinv_src(src, p, q) : (p == q ? 1.0 : 0.0);
-      M[a][b] = v;
+      for (int b = 0; b < T; ++b) {
+        const int p = r + G * a, q = c + G * b;
+        double v = 0.0;
+        if (worker && p >= q) v = (p < n) ? cholinv_src(src, p, q) : (p == q ? 1.0 : 0.0);
+        M[a][b] = v;
+      }
+  } else {
+    // the sum of the partial Grams, split by split (the same order per entry
+    // as cholinv_src: from 0, splits ascending), with the loads of a quarter
+    // of the tile (two rows) of one split in flight together
+    const int64_t stride = (int64_t)src.nblk * 16;
+#pragma unroll
+    for (int a = 0; a < T; ++a)
+#pragma unroll
+      for (int b = 0; b < T; ++b) {
+        const int p = r + G * a, q = c + G * b;
+        M[a][b] = (worker && p >= q && p >= n && p == q) ? 1.0 : 0.0;
+      }
+    for (int k = 0; k < src.splits; ++k) {
+      const double* base = src.part + k * stride;
+
+      constexpr int RH = T >= 4 ? T / 4 : 1;  // rows per batch
+#pragma unroll
+      for (int h = 0; h < T / RH; ++h) {
+        double x[RH][T];
+#pragma unroll
+        for (int a = 0; a < RH; ++a)
+#pragma unroll
+          for (int b = 0; b < T; ++b) {
+            const int p = r + G * (h * RH + a), q = c + G * b;
+            const int I = p >> 2, J = q >> 2;
+            const int off = (I * (I + 1) / 2 + J) * 16 + (p & 3) * 4 + (q & 3);  // < 16 nblk
+            x[a][b] = (worker && p >= q && p < n) ? base[off] : 0.0;
+          }
+#pragma unroll
+        for (int a = 0; a < RH; ++a)
+#pragma unroll
+          for (int b = 0; b < T; ++b) M[h * RH + a][b] += x[a][b];
+      }
     }
+  }
 
   if (fail == 0) {
     int step = 0;
