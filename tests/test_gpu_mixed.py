@@ -37,6 +37,7 @@ def mixed_factor(lib, a):
     (4096, 64, 1e3, 51), (20000, 33, 1e6, 52), (262144 // 8, 256, 1e2, 53), (262144 // 8, 256, 1e4, 54),
     (262144 // 8, 256, 1e6, 55), (262144 // 8, 256, 1e7, 56), (3001, 300, 1e5, 57), (1000, 17, 1e3, 58),
     (8192, 520, 1e4, 59),  # n > 256 with m % 4 == 0: the FP32 Q1's Gram takes the direct-copy path
+    (10000, 128, 1e4, 60), (7777, 100, 1e6, 61),  # 64 < n <= 128: the 128-column kernels, a ragged tail
 ])
 def test_mixed_gates_against_fp64_oracle(gpu_lib, m, n, kappa, seed):
     a = gdv_matrix(m, n, kappa, seed)
