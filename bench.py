@@ -261,6 +261,50 @@ def serve_stream(cq, torch, count: int, rate: float, seed: int):
     }
 
 
+BATCHED_SHAPES = ((256, 4096, 128), (64, 16384, 256), (512, 2048, 32))  # (count, m, n)
+
+
+def batched_leg(cq, torch, steps: int = 5, warmup: int = 2):
+    """cqr2_factor_batched on sets of equal-shape problems (A = randn, column-major,
+    generated on the device): ms per call, problems/s and CholeskyQR2 GFLOP/s of the
+    whole batch, and the device checks of its first and last problem."""
+    lib = cq.load()
+    dev = torch.device("cuda:0")
+    sp = cq.ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    rows = []
+    for count, m, n in BATCHED_SHAPES:
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(7 * m + n)
+        mats = [torch.randn((n, m), generator=gen, device=dev, dtype=torch.float64).t() for _ in range(count)]
+        qs = [cq.empty_colmajor(m, n, device=dev) for _ in range(count)]
+        rs = [cq.empty_colmajor(n, n, device=dev) for _ in range(count)]
+        probs = [cq.problem(a, q, r, None) for a, q, r in zip(mats, qs, rs)]
+        arr = (cq.Problem * count)(*probs)
+        wb = lib.cqr2_batched_workspace_size(arr, count, cq.CQR2_FP64)
+        work = torch.empty(max(int(wb), 256), dtype=torch.uint8, device=dev)
+
+        def call():
+            rc = lib.cqr2_factor_batched(arr, count, cq._ptr(work), work.numel(), cq.CQR2_FP64, sp)
+            if rc != 0:
+                raise cq.CQR2Error(rc, "cqr2_factor_batched")
+        for _ in range(warmup):
+            call()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            call()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        flops = count * (4.0 * m * n * n + 5.0 * n ** 3 / 3.0)
+        checks = [device_checks(torch, mats[i], qs[i], rs[i]) for i in (0, count - 1)]
+        rows.append({"problems": count, "m": m, "n": n, "ms_per_call": round(ms, 4),
+                     "problems_per_s": round(count / (ms / 1e3), 1), "gflops": round(flops / (ms / 1e3) / 1e9, 1),
+                     "checks": checks})
+        log(f"batched {count} x {m}x{n}: {ms:.3f} ms per call")
+        del mats, qs, rs, work
+    return rows
+
+
 def mixed_sweep(cq, torch, steps: int, warmup: int):
     """The 262144 x 256 comparison problem (A = G D V, generated on the device)
     at each condition number of the sweep: CholeskyQR2 in plain FP64 and with pass 1's Q1 in FP32
@@ -498,6 +542,7 @@ def main():
     if default_run and not args.no_mixed_sweep:
         out["mixed_vs_fp64"] = mixed_sweep(cq, torch, steps=10, warmup=2)
     if default_run and not args.no_serve:
+        out["batched"] = batched_leg(cq, torch)
         out["serving"] = serve_stream(cq, torch, args.serve_requests, args.serve_rate, SERVE_SEED)
     if default_run and not args.no_cpu_baseline:
         log("timing the CPU oracle ...")

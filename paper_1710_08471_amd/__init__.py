@@ -329,8 +329,9 @@ def problem(A, Q, R, info=None) -> Problem:
 def factor_batched(As, infos=None):
     """[(Q, R), ...] = CholeskyQR2 of every matrix in `As` (cqr2_factor_batched).
 
-    Problems with n <= 128 share six multi-problem launches; larger ones run
-    the tiled path in turn.  `infos`: optional int32 device tensor of len(As).
+    Problems with n <= 256 share the multi-problem step launches (six, or
+    eight when a problem has n > 128); larger ones run the tiled path in turn.
+    `infos`: optional int32 device tensor of len(As).
     """
     import torch
     lib = load()
