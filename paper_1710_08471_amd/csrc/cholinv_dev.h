@@ -89,7 +89,7 @@ __device__ __forceinline__ double cholinv_src(const CholInvSrc& s, int p, int q)
 // Threads tid < G*G do the work; any further threads of the workgroup run
 // the same loop as shadows (the same barriers and pivot tests, no element
 // updates, no stores) so the body can sit in a workgroup larger than the
-// grid.  colbuf: 2 * B * G * T doubles of LDS.
+// grid.  colbuf: (2 B + 1) G T doubles of LDS.
 template <int T, int G, int B>
 __device__ __forceinline__ void cholinv_body(const CholInvSrc& src, int n, double* __restrict__ R, int64_t ldr,
                                              double* __restrict__ Rinv, int64_t ldri, double* __restrict__ Upad,
@@ -105,6 +105,10 @@ __device__ __forceinline__ void cholinv_body(const CholInvSrc& src, int n, doubl
   if (info != nullptr && *info != 0) fail = -1;  // an earlier phase failed: skip, NaN outputs
 
   double M[T][T];
+  // Y(j, j) for j < n, after the colbuf panels: the same reciprocal square
+  // root the off-diagonal recurrences used, written and later read by the
+  // owner of the diagonal entry
+  double* ydiag = colbuf_ + 2 * B * NP;
   if (src.part == nullptr) {
 #pragma unroll
     for (int a = 0; a < T; ++a)
@@ -253,6 +257,7 @@ __device__ __forceinline__ void cholinv_body(const CholInvSrc& src, int n, doubl
               for (int i = 0; i < B; ++i)
                 if (pp == i) val = i > kk ? Lb[i][kk] : (i == kk ? sd[kk] : Yb[kk][i]);
               M[a][jb] = val;
+              if (pp == kk) ydiag[j0 + kk] = y[kk];  // Y(j, j): the reciprocal the recurrences used
             }
           }
           // rank-B update of every element right of the block: below the
@@ -302,14 +307,14 @@ __device__ __forceinline__ void cholinv_body(const CholInvSrc& src, int n, doubl
             Rinv[p + (int64_t)q * ldri] = fail ? nan : v;
             Rinv[q + (int64_t)p * ldri] = 0.0;
           } else if (p == q) {
-            Rinv[p + (int64_t)p * ldri] = fail ? nan : 1.0 / v;
+            Rinv[p + (int64_t)p * ldri] = fail ? nan : ydiag[p];
           }
         }
       }
       if (Upad != nullptr && p < np && q < np) {
         double u = 0.0;
         if (p < q) u = v;
-        else if (p == q) u = 1.0 / v;
+        else if (p == q) u = p < n ? ydiag[p] : 1.0;
         Upad[(int64_t)p * np + q] = fail ? nan : u;
       }
     }

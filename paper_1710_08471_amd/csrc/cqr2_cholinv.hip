@@ -21,7 +21,7 @@ __global__ __launch_bounds__(G * G) void k_cholinv(const double* __restrict__ W,
                                                  int64_t ldri, double* __restrict__ Upad, int np,
                                                  int32_t* __restrict__ info, int info_offset) {
   constexpr int B = cholinv_block<T>();
-  __shared__ double colbuf[2 * B * G * T];
+  __shared__ double colbuf[(2 * B + 1) * G * T];
   const CholInvSrc src{W, ldw, nullptr, 0, 0};
   cholinv_body<T, G, B>(src, n, R, ldr, Rinv, ldri, Upad, np, info, info_offset, colbuf);
 }
