@@ -59,14 +59,18 @@ extern "C" {
 #define CQR2_ERR_UNSUPPORTED (-101)
 
 /* flags */
+/* Plain FP64 CholeskyQR2.  Pass 2's Gram is fused into pass 1's Q1 = A R1^{-1}
+ * wherever that pays (64 < n <= 128: one launch forms Q1 and the partial Grams
+ * of its stored values); there is no flag for it. */
 #define CQR2_FP64 0u
 /* Pass 1's Q1 = A R1^{-1} in FP32 arithmetic (A and R1^{-1} rounded to FP32,
  * FP32 MFMA products and sums) with an FP32 Q1 of m*n*4 bytes in the
  * workspace; the Gram matrices, CholInv and all of pass 2 stay FP64, and pass 2
  * factors the stored FP32 Q1 widened exactly.  Orthogonality is recovered by
  * pass 2 (the FP64 gate holds); the residual ||A - QR||/||A|| and R are
- * accurate to the FP32 rounding level only.  Runs the tiled path at every n.
- * Accepted by cqr2_factor_ex / cqr2_workspace_size. */
+ * accurate to the FP32 rounding level only.  Runs the general path at every n
+ * (128- or 256-column MFMA 16x16x4 kernels up to n = 256, the tiled kernels
+ * above).  Accepted by cqr2_factor_ex / cqr2_workspace_size. */
 #define CQR2_MIXED_P1_FP32 1u
 
 /* Shifted CholeskyQR3, the unconditionally stable extension of CholeskyQR2
