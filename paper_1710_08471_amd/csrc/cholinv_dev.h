@@ -225,13 +225,18 @@ __device__ __forceinline__ void cholinv_body(const CholInvSrc& src, int n, doubl
               for (int ii = 0; ii < jj; ++ii) t = fma(-Lb[jj][ii], v[a][ii], t);
               v[a][jj] = t * y[jj];
             }
-            const int pp = p - j0;  // register arrays take compile-time indices only
+            // p - j0 = G (a - jb) + (r - jc0) with r, jc0 in [0, G) and jc0 <= G - B:
+            // negative for a < jb, at least B for a > jb, so only the register
+            // row a == jb (both compile-time here) can hold rows of the block
+            if (a == jb) {
+              const int pp = p - j0;  // register arrays take compile-time indices only
 #pragma unroll
-            for (int i = 0; i < B; ++i)
-              if (pp == i) {
+              for (int i = 0; i < B; ++i)
+                if (pp == i) {
 #pragma unroll
-                for (int jj = 0; jj < B; ++jj) v[a][jj] = jj >= i ? Yb[jj][i] : 0.0;
-              }
+                  for (int jj = 0; jj < B; ++jj) v[a][jj] = jj >= i ? Yb[jj][i] : 0.0;
+                }
+            }
           }
           // columns right of the block: L(q, j)
           double lq[T][B];
@@ -251,13 +256,15 @@ __device__ __forceinline__ void cholinv_body(const CholInvSrc& src, int n, doubl
             if (c != jc0 + kk) continue;
 #pragma unroll
             for (int a = 0; a < T; ++a) {
-              const int pp = r + G * a - j0;
               double val = v[a][kk];  // L(p, j) below the block, Y(j, p) above it
+              if (a == jb) {  // the only register row that can hold rows of the block (see above)
+                const int pp = r + G * a - j0;
 #pragma unroll
-              for (int i = 0; i < B; ++i)
-                if (pp == i) val = i > kk ? Lb[i][kk] : (i == kk ? sd[kk] : Yb[kk][i]);
+                for (int i = 0; i < B; ++i)
+                  if (pp == i) val = i > kk ? Lb[i][kk] : (i == kk ? sd[kk] : Yb[kk][i]);
+                if (pp == kk) ydiag[j0 + kk] = y[kk];  // Y(j, j): the reciprocal the recurrences used
+              }
               M[a][jb] = val;
-              if (pp == kk) ydiag[j0 + kk] = y[kk];  // Y(j, j): the reciprocal the recurrences used
             }
           }
           // rank-B update of every element right of the block: below the
@@ -267,13 +274,16 @@ __device__ __forceinline__ void cholinv_body(const CholInvSrc& src, int n, doubl
           const bool low_diag = r >= c;              // element (a, a) of this thread lies on or below the diagonal
 #pragma unroll
           for (int a = 0; a < T; ++a) {
-            const bool row_up = r + G * a < j0 + B;
+            // rows above or inside the block: all of a < jb, none of a > jb (see above)
+            const bool row_up = a < jb ? true : (a > jb ? false : r + G * a < j0 + B);
             double vu[B];
 #pragma unroll
             for (int jj = 0; jj < B; ++jj) vu[jj] = row_up ? v[a][jj] : 0.0;
 #pragma unroll
             for (int b = jb; b < T; ++b) {
               if (b == jb && !right_of_block) continue;
+              // rows below the block (a > jb) above the diagonal (b > a): Y(., p) = 0, no update
+              if (a > jb && b > a) continue;
               double t = M[a][b];
 #pragma unroll
               for (int jj = 0; jj < B; ++jj) {
