@@ -100,6 +100,37 @@ def test_cholinv_matches_lapack(n, kappa):
     assert np.linalg.norm(y @ l - np.eye(n)) <= 10 * n * U * cw ** 0.5 * 10
 
 
+@pytest.mark.parametrize("n", [130, 200, 256])
+def test_cholinv_split_at_128_matches_oracle(n):
+    """The GPU's one-workgroup CholInv for 128 < n <= 256 (and the recursion
+    above 128) splits W at h = 128, not at floor(n/2): R11 and R11^-1 from
+    CholInv(W11), R12 = R11^-T W12, the Schur complement S = W22 - R12^T R12,
+    R22 and R22^-1 from CholInv(S), and (R^-1)12 = -R11^-1 R12 R22^-1.  In
+    exact arithmetic that is the same factor and inverse as Algorithm 2's
+    halving (the Cholesky factor is unique); here the block equations, written
+    with the oracle's CholInv on the diagonal blocks, agree with the oracle to
+    rounding, and a sign slip in the coupling block is caught."""
+    a = gdv_matrix(3 * n, n, 1e3, 300 + n)
+    w = oracle.syrk(a)
+    l, y = oracle.cholinv(w)
+    h = 128
+    l11, y11 = oracle.cholinv(w[:h, :h])
+    r11, ri11 = l11.T, y11.T
+    r12 = ri11.T @ w[:h, h:]
+    s = w[h:, h:] - r12.T @ r12
+    l22, y22 = oracle.cholinv(s)
+    r22, ri22 = l22.T, y22.T
+    ri12 = -(ri11 @ r12) @ ri22
+    r = np.block([[r11, r12], [np.zeros((n - h, h)), r22]])
+    ri = np.block([[ri11, ri12], [np.zeros((n - h, h)), ri22]])
+    tol = 50 * n * U * np.linalg.cond(w)
+    assert oracle.rel_fro(r, l.T) <= tol
+    assert oracle.rel_fro(ri, y.T) <= tol
+    assert np.linalg.norm(ri @ r - np.eye(n)) <= tol * n
+    wrong = np.block([[ri11, -ri12], [np.zeros((n - h, h)), ri22]])
+    assert oracle.rel_fro(wrong, y.T) > 1e-3
+
+
 def test_cholinv_breakdown_columns():
     d = _gold("cholinv_exact_n8.json")
     w = np.array(d["W"])
