@@ -20,6 +20,10 @@
  *    cqr2_apply_rinv_f32) synchronizes the device once when that workspace
  *    has to grow, and the batched call and the server wait for a pinned
  *    task-table staging buffer when the host runs several calls ahead.
+ *    The CholInv of n >= 512 (at full inverse depth) fans its bulk products
+ *    out to two streams of the library (per device, default priority, not
+ *    blocking on the null stream) through events and joins them back into
+ *    `stream` before any later work on it; its order on `stream` is kept.
  *  - Ownership: the caller owns A, Q, R, work and d_info.  A is read-only.
  *    Q and R must not overlap A or each other (checked on address ranges).
  *    The library never frees caller memory.

@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 #include <cmath>
 #include <cstdint>
+#include <mutex>
+#include <vector>
 
 namespace cqr2 {
 
@@ -38,9 +40,75 @@ int inverse_blocks(int64_t n, int depth, Block* out, int cap) {
 // Reduction splits used by every GEMM of the recursion, fixed by the shape only.
 static int rec_splits(int64_t M, int64_t N, int64_t K) { return gemm_pick_splits(M, N, K, kPlanCUs); }
 
+// ---- The recursion unrolled into 128-column blocks, with look-ahead --------
+// Algorithm 2 splits W at any h; taking h = 128 at every level turns the
+// recursion into a loop over the 128-column blocks k of W (a right-looking
+// Cholesky that carries the inverse along):
+//   base(k)   R_kk and R_kk^-1 from the updated diagonal block (one workgroup);
+//   panel(k)  R_{k,>k} = R_kk^-T W_{>k,k}^T;
+//   update(k) W_{>k,>k} -= R_{k,>k}^T R_{k,>k}  (lower triangle);
+// and the off-diagonal blocks of the inverse come from the block form of the
+// same equations on the leading (k+1) blocks, split before block k:
+//   inv(k)    R^-1_{<k,k} = -R^-1_{<k,<k} (R_{<k,k} R_kk^-1).
+// The only serial chain is the diagonal blocks.  The caller's stream runs
+// base(k), panel(k) and the update of the diagonal block k + 1 by steps k - 1
+// and k together (one product over block rows k - 1 and k of R), then
+// base(k + 1).  Stream B runs the rest of update(k): first block column
+// k + 1 below its diagonal block (the next panel's input), then the trailing
+// lower triangle below block row k + 2 (one launch of the tiled SYRK in
+// update mode).  Stream C runs inv(k).  Each block of W takes every step's
+// update exactly once.  Events order every pair of steps that touch the same
+// block:
+//   B waits for panel(k) before its part of step k;
+//   the caller's stream waits for B's first part of step k - 1 before
+//   panel(k), and for its second part of step k - 2 before updating the
+//   diagonal block k + 1;
+//   C waits for base(k), which follows every panel that wrote R_{<k,k};
+//   the caller's stream joins B and C at the end.
+// Used for n >= kLookaheadMinN at full inverse depth.
+constexpr int64_t kLookaheadMinN = 512;
+
+struct LookaheadLayout {
+  size_t a_ws, b_ws, c_x, c_ws, total;  // offsets of the three streams' scratch, and the total
+};
+
+static size_t la_align(size_t x) { return (x + 255) / 256 * 256; }
+
+// Reduction splits of the chain's small products (128 x 128 x 128): the
+// split product and its sum finish sooner than four long-K workgroups.
+static int la_splits_a(int64_t M, int64_t N, int64_t K) { return rec_splits(M, N, K); }
+
+static LookaheadLayout lookahead_layout(int64_t n) {
+  size_t a = 0, b = 0, cx = 0, cw = 0;
+  auto mx = [](size_t& v, size_t x) { v = x > v ? x : v; };
+  for (int64_t c0 = 0; c0 < n; c0 += kBaseN) {
+    const int64_t bk = n - c0 < kBaseN ? n - c0 : kBaseN, c1 = c0 + bk, r1 = n - c1;
+    if (r1 > 0) {
+      const int64_t b1 = r1 < kBaseN ? r1 : kBaseN, r2 = r1 - b1;
+      mx(a, gemm_workspace_bytes(bk, r1, rec_splits(bk, r1, bk)));
+      mx(a, gemm_workspace_bytes(b1, b1, la_splits_a(b1, b1, 2 * kBaseN)));
+      mx(a, gemm_workspace_bytes(b1, b1, la_splits_a(b1, b1, bk)));
+      if (r2 > 0) mx(b, gemm_workspace_bytes(r2, b1, rec_splits(r2, b1, bk)));
+    }
+    if (c0 > 0) {
+      mx(cx, (size_t)c0 * bk * sizeof(double));
+      mx(cw, gemm_workspace_bytes(c0, bk, rec_splits(c0, bk, bk)));
+      mx(cw, gemm_workspace_bytes(c0, bk, rec_splits(c0, bk, c0)));
+    }
+  }
+  LookaheadLayout L{};
+  L.a_ws = 0;
+  L.b_ws = la_align(a);
+  L.c_x = L.b_ws + la_align(b);
+  L.c_ws = L.c_x + la_align(cx);
+  L.total = L.c_ws + la_align(cw);
+  return L;
+}
+
 size_t cholinv_rec_workspace(int64_t n) {
   // scratch T (h x n2 <= n*n/4) + the largest GEMM split workspace of the recursion
   if (n <= kBaseN) return 0;
+  const size_t la = n >= kLookaheadMinN ? lookahead_layout(n).total : 0;
   const int64_t h = cholinv_split(n), n2 = n - h;
   size_t ws = 0;
   auto upd = [&](int64_t M, int64_t N, int64_t K) {
@@ -53,7 +121,8 @@ size_t cholinv_rec_workspace(int64_t n) {
   const size_t inner = cholinv_rec_workspace(h) > cholinv_rec_workspace(n2) ? cholinv_rec_workspace(h)
                                                                             : cholinv_rec_workspace(n2);
   const size_t mine = (size_t)h * n2 * sizeof(double) + ws;
-  return mine > inner ? mine : inner;
+  const size_t rec = mine > inner ? mine : inner;
+  return rec > la ? rec : la;
 }
 
 __global__ void k_zero_block(double* X, int64_t ldx, int64_t rows, int64_t cols) {
@@ -88,11 +157,129 @@ __global__ void k_zero_lower2(double* R, int64_t ldr, double* Rinv, int64_t ldri
   Rinv[i + j * ldri] = 0.0;
 }
 
+// Helper streams and events of the look-ahead form, one set per device,
+// created on first use and kept until the process ends: B and C carry the
+// bulk products next to the chain on the caller's stream.  They run at the
+// default priority and do not synchronize with the null stream.  The mutex
+// keeps one factorization's records and waits together when several host
+// threads enqueue.
+struct LookaheadStreams {
+  std::mutex mu;
+  hipStream_t b = nullptr, c = nullptr;
+  std::vector<hipEvent_t> ev;
+};
+constexpr int kMaxDevices = 64;
+static LookaheadStreams g_la[kMaxDevices];
+
+static hipError_t lookahead_events(LookaheadStreams& L, size_t count) {
+  if (L.b == nullptr) CQR2_HIP(hipStreamCreateWithFlags(&L.b, hipStreamNonBlocking));
+  if (L.c == nullptr) CQR2_HIP(hipStreamCreateWithFlags(&L.c, hipStreamNonBlocking));
+  while (L.ev.size() < count) {
+    hipEvent_t e;
+    CQR2_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    L.ev.push_back(e);
+  }
+  return hipSuccess;
+}
+
+static hipError_t cholinv_lookahead(double* W, int64_t ldw, int64_t n, double* R, int64_t ldr, double* Rinv,
+                                    int64_t ldri, char* work, int32_t* info, int info_offset, hipStream_t s) {
+  int dev = 0;
+  CQR2_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  LookaheadStreams& L = g_la[dev];
+  std::lock_guard<std::mutex> lock(L.mu);
+  const int64_t nb = (n + kBaseN - 1) / kBaseN;
+  // events: D_k (base k done, k >= 1), P_k (panel k done), T1_k and T2_k
+  // (B's two parts of update k done), and the joins of B and C
+  CQR2_HIP(lookahead_events(L, (size_t)(4 * nb + 2)));
+  hipEvent_t* evD = L.ev.data();
+  hipEvent_t* evP = evD + nb;
+  hipEvent_t* evT1 = evP + nb;
+  hipEvent_t* evT2 = evT1 + nb;
+  hipEvent_t joinB = evT2[nb], joinC = evT2[nb + 1];
+  const LookaheadLayout lay = lookahead_layout(n);
+  double* wsA = (double*)(work + lay.a_ws);
+  double* wsB = (double*)(work + lay.b_ws);
+  double* X = (double*)(work + lay.c_x);
+  double* wsC = (double*)(work + lay.c_ws);
+  auto blk = [&](int64_t k, int64_t& c0, int64_t& bk) {
+    c0 = k * kBaseN;
+    bk = n - c0 < kBaseN ? n - c0 : kBaseN;
+  };
+  bool b_used = false, c_used = false;
+  std::vector<char> has_b((size_t)nb, 0);  // step k ran work on B
+  for (int64_t k = 0; k < nb; ++k) {
+    int64_t c0, bk;
+    blk(k, c0, bk);
+    const int64_t c1 = c0 + bk, r1 = n - c1;
+    double* Rkk = R + c0 + c0 * ldr;
+    double* Rikk = Rinv + c0 + c0 * ldri;
+    CQR2_HIP(launch_cholinv(W + c0 + c0 * ldw, ldw, (int)bk, Rkk, ldr, Rikk, ldri, nullptr, 0, info,
+                            info_offset + (int)c0, s));
+    if (k >= 1) {
+      // inv(k) on stream C: X = R_{<k,k} R_kk^-1, then R^-1_{<k,k} = -R^-1_{<k,<k} X
+      CQR2_HIP(hipEventRecord(evD[k], s));
+      CQR2_HIP(hipStreamWaitEvent(L.c, evD[k], 0));
+      CQR2_HIP(launch_gemm(0, 0, c0, bk, bk, 1.0, R + c0 * ldr, ldr, Rikk, ldri, 0.0, X, c0, GEMM_B_UPPER,
+                           rec_splits(c0, bk, bk), wsC, info, L.c));
+      CQR2_HIP(launch_gemm(0, 0, c0, bk, c0, -1.0, Rinv, ldri, X, c0, 0.0, Rinv + c0 * ldri, ldri, GEMM_A_UPPER,
+                           rec_splits(c0, bk, c0), wsC, info, L.c));
+      c_used = true;
+    }
+    if (r1 <= 0) break;
+    const int64_t b1 = r1 < kBaseN ? r1 : kBaseN, c2 = c1 + b1, r2 = n - c2;
+    double* Rk1 = R + c0 + c1 * ldr;  // R_{k,>k}: bk x r1
+    double* Rk2 = R + c0 + c2 * ldr;  // R_{k,>k+1}: bk x r2
+    // panel(k) reads block column k below the diagonal, which B's first part
+    // of step k - 1 wrote last
+    if (k >= 1 && has_b[k - 1]) CQR2_HIP(hipStreamWaitEvent(s, evT1[k - 1], 0));
+    // panel(k): R_{k,>k} = R_kk^-T W_{>k,k}^T
+    CQR2_HIP(launch_gemm(1, 1, bk, r1, bk, 1.0, Rikk, ldri, W + c1 + c0 * ldw, ldw, 0.0, Rk1, ldr, GEMM_A_LOWER,
+                         rec_splits(bk, r1, bk), wsA, info, s));
+    if (r2 > 0) {
+      // on stream B, update(k) below block row k + 1: first block column
+      // k + 1 (the next panel's input), then the trailing lower triangle
+      // below block row k + 2 in one launch of the tiled SYRK in update mode
+      // (the diagonal block k + 2 takes update(k) on the caller's stream,
+      // together with update(k + 1))
+      CQR2_HIP(hipEventRecord(evP[k], s));
+      CQR2_HIP(hipStreamWaitEvent(L.b, evP[k], 0));
+      CQR2_HIP(launch_gemm(1, 0, r2, b1, bk, -1.0, Rk2, ldr, Rk1, ldr, 1.0, W + c2 + c1 * ldw, ldw, 0,
+                           rec_splits(r2, b1, bk), wsB, info, L.b));
+      CQR2_HIP(hipEventRecord(evT1[k], L.b));
+      CQR2_HIP(launch_syrk_update(Rk2, bk, (int)r2, ldr, -1.0, W + c2 + c2 * ldw, ldw, 1, info, L.b));
+      CQR2_HIP(hipEventRecord(evT2[k], L.b));
+      has_b[k] = 1;
+      b_used = true;
+    }
+    // the diagonal block k + 1, the next link of the chain, takes update(k)
+    // and update(k - 1) in one product (block rows k - 1 and k of R are
+    // adjacent); B's second part of step k - 2 wrote the block before
+    if (k >= 2 && has_b[k - 2]) CQR2_HIP(hipStreamWaitEvent(s, evT2[k - 2], 0));
+    const int64_t kr = k >= 1 ? 2 * kBaseN : bk;
+    double* Rd = R + (c1 - kr) + c1 * ldr;
+    CQR2_HIP(launch_gemm(1, 0, b1, b1, kr, -1.0, Rd, ldr, Rd, ldr, 1.0, W + c1 + c1 * ldw, ldw, GEMM_C_LOWER,
+                         la_splits_a(b1, b1, kr), wsA, info, s));
+  }
+  if (b_used) {
+    CQR2_HIP(hipEventRecord(joinB, L.b));
+    CQR2_HIP(hipStreamWaitEvent(s, joinB, 0));
+  }
+  if (c_used) {
+    CQR2_HIP(hipEventRecord(joinC, L.c));
+    CQR2_HIP(hipStreamWaitEvent(s, joinC, 0));
+  }
+  return hipSuccess;
+}
+
 // The recursion proper: the strictly lower blocks off the diagonal are left
 // for the caller (cholinv_recursive zeroes them all in one launch).
 static hipError_t cholinv_rec(double* W, int64_t ldw, int64_t n, double* R, int64_t ldr, double* Rinv, int64_t ldri,
                               char* work, int32_t* info, int info_offset, hipStream_t s, int depth) {
   if (n <= kBaseN) return launch_cholinv(W, ldw, (int)n, R, ldr, Rinv, ldri, nullptr, 0, info, info_offset, s);
+  if (depth == 0 && n >= kLookaheadMinN)
+    return cholinv_lookahead(W, ldw, n, R, ldr, Rinv, ldri, work, info, info_offset, s);
   const int64_t h = cholinv_split(n), n2 = n - h;
   double* W22 = W + h + h * ldw;
   double* R12 = R + h * ldr;

@@ -166,21 +166,41 @@ __global__ __launch_bounds__(256, 2) void k_gemm(GemmArgs g) {
   }
 
   const int orow = 4 * ((lane >> 2) & 3) + (lane >> 4), ocol = lane & 3;
+  auto out_ok = [&](int rt, int cg) {
+    const int64_t i = i0 + wr + 16 * rt + orow, j = j0 + wc + 4 * cg + ocol;
+    if (i >= g.M || j >= g.N) return false;
+    if ((g.flags & GEMM_C_LOWER) && i < j) return false;
+    if ((g.flags & GEMM_C_UPPER) && i > j) return false;
+    return true;
+  };
+  if (g.splits > 1) {
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int cg = 0; cg < 8; ++cg) {
+        const int64_t i = i0 + wr + 16 * rt + orow, j = j0 + wc + 4 * cg + ocol;
+        if (out_ok(rt, cg)) g.partial[(int64_t)split * g.ldp * g.N + i + j * g.ldp] = acc[rt][cg];
+      }
+    return;
+  }
+  // with beta != 0 every old value of C is loaded before the first store (a
+  // store could alias a later load as far as the compiler knows)
+  double old[2][8];
 #pragma unroll
   for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
     for (int cg = 0; cg < 8; ++cg) {
       const int64_t i = i0 + wr + 16 * rt + orow, j = j0 + wc + 4 * cg + ocol;
-      if (i >= g.M || j >= g.N) continue;
-      if ((g.flags & GEMM_C_LOWER) && i < j) continue;
-      if ((g.flags & GEMM_C_UPPER) && i > j) continue;
-      if (g.splits > 1) {
-        g.partial[(int64_t)split * g.ldp * g.N + i + j * g.ldp] = acc[rt][cg];
-      } else {
-        const double v = g.alpha * acc[rt][cg];
-        double* cp = (double*)g.C + i + j * g.ldc;
-        *cp = (g.beta == 0.0) ? v : v + g.beta * *cp;
-      }
+      old[rt][cg] = (g.beta != 0.0 && out_ok(rt, cg)) ? ((const double*)g.C)[i + j * g.ldc] : 0.0;
+    }
+#pragma unroll
+  for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+    for (int cg = 0; cg < 8; ++cg) {
+      const int64_t i = i0 + wr + 16 * rt + orow, j = j0 + wc + 4 * cg + ocol;
+      if (!out_ok(rt, cg)) continue;
+      const double v = g.alpha * acc[rt][cg];
+      ((double*)g.C)[i + j * g.ldc] = (g.beta == 0.0) ? v : v + g.beta * old[rt][cg];
     }
 }
 

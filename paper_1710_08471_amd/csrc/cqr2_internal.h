@@ -166,6 +166,11 @@ SyrkPlan plan_syrk(int64_t m, int64_t n);
 // Lower triangle of W = AᵀA (any n; A FP64, or FP32 when a_f32, widened exactly).
 hipError_t launch_syrk(const SyrkPlan& p, int a_f32, const void* A, int64_t m, int n, int64_t lda, double* partials,
                        double* W, int64_t ldw, const int32_t* info, hipStream_t s);
+// W(i, j) += alpha (AᵀA)(i, j) for j <= i < n, A m x n (lda), in one launch
+// of 128 x 256 tiles (no partials; m is the whole reduction, meant for
+// m <= a few hundred).  skip_first_block_row leaves rows 0..127 of W alone.
+hipError_t launch_syrk_update(const double* A, int64_t m, int n, int64_t lda, double alpha, double* W, int64_t ldw,
+                              int skip_first_block_row, const int32_t* info, hipStream_t s);
 
 // ---- recursive CholInv and the n > 128 driver --------------------------------
 int64_t cholinv_split(int64_t n);

@@ -207,10 +207,13 @@ static int syrk_ntiles(int64_t n) {
   return (int)c;
 }
 
-template <typename TA>
-__global__ __launch_bounds__(512, 1) void k_syrk_tile(const TA* __restrict__ A, int64_t m, int n, int64_t lda,
-                                                      int64_t chunks_per_split, double* __restrict__ partials,
-                                                      int ntiles, const int32_t* __restrict__ info) {
+// UPDATE: one split over all of m, and the tile goes straight into W:
+// W(i, j) += alpha (AᵀA)(i, j) for j <= i < n; tiles from tile_base on (tile
+// 0 is the leading 128 x 128 diagonal block).
+template <typename TA, bool UPDATE>
+__device__ __forceinline__ void syrk_tile_body(const TA* __restrict__ A, int64_t m, int n, int64_t lda,
+                                               int64_t chunks_per_split, double* __restrict__ partials, int ntiles,
+                                               int tile_base, double alpha, double* __restrict__ W, int64_t ldw) {
   constexpr int kES = (int)sizeof(TA);
   constexpr int kIBytes = kSyK * kSyI * kES, kJBytes = kSyK * kSyJ * kES, kBufBytes = kIBytes + kJBytes;
   // one copy moves 16 bytes per lane: 8 columns of FP64 or 16 of FP32
@@ -218,9 +221,8 @@ __global__ __launch_bounds__(512, 1) void k_syrk_tile(const TA* __restrict__ A, 
   constexpr int kICopies = kSyI / kColsPerCopy / 8, kJCopies = kSyJ / kColsPerCopy / 8;  // per wave
   constexpr int kPerChunk = kICopies + kJCopies;
   __shared__ __attribute__((aligned(16))) char smem[kSyBufs * kBufBytes];
-  if (info != nullptr && *info != 0) return;
   int ti, tj;
-  syrk_tile((int)blockIdx.x, ti, tj);
+  syrk_tile((int)blockIdx.x + tile_base, ti, tj);
   const int I0 = kSyI * ti, J0 = kSyJ * tj;
   const int64_t total_chunks = (m + kSyK - 1) / kSyK;
   const int64_t cb = (int64_t)blockIdx.y * chunks_per_split;
@@ -318,12 +320,48 @@ __global__ __launch_bounds__(512, 1) void k_syrk_tile(const TA* __restrict__ A, 
       }
     }
   }
-  // lane-major partial block: entry (rt, cg) of lane l at (rt 16 + cg) 64 + l
-  double* out = partials + ((int64_t)blockIdx.y * ntiles + blockIdx.x) * kSyTile + wave * kSyWave;
+  if constexpr (UPDATE) {
+    if (!live) return;
+    // a row tile's 16 values of W are all loaded before any is stored (the
+    // stores could alias later loads as far as the compiler knows)
 #pragma unroll
-  for (int rt = 0; rt < 4; ++rt)
+    for (int rt = 0; rt < 4; ++rt) {
+      const int i = I0 + wr + 16 * rt + 4 * ((lane >> 2) & 3) + (lane >> 4);
+      double w[16];
 #pragma unroll
-    for (int cg = 0; cg < 16; ++cg) out[(rt * 16 + cg) * 64 + lane] = acc[rt][cg];
+      for (int cg = 0; cg < 16; ++cg) {
+        const int j = J0 + wc + 4 * cg + (lane & 3);
+        w[cg] = (i < n && j <= i) ? W[i + (int64_t)j * ldw] : 0.0;
+      }
+#pragma unroll
+      for (int cg = 0; cg < 16; ++cg) {
+        const int j = J0 + wc + 4 * cg + (lane & 3);
+        if (i < n && j <= i) W[i + (int64_t)j * ldw] = fma(alpha, acc[rt][cg], w[cg]);
+      }
+    }
+  } else {
+    // lane-major partial block: entry (rt, cg) of lane l at (rt 16 + cg) 64 + l
+    double* out = partials + ((int64_t)blockIdx.y * ntiles + blockIdx.x) * kSyTile + wave * kSyWave;
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+      for (int cg = 0; cg < 16; ++cg) out[(rt * 16 + cg) * 64 + lane] = acc[rt][cg];
+  }
+}
+
+template <typename TA>
+__global__ __launch_bounds__(512, 1) void k_syrk_tile(const TA* __restrict__ A, int64_t m, int n, int64_t lda,
+                                                      int64_t chunks_per_split, double* __restrict__ partials,
+                                                      int ntiles, const int32_t* __restrict__ info) {
+  if (info != nullptr && *info != 0) return;
+  syrk_tile_body<TA, false>(A, m, n, lda, chunks_per_split, partials, ntiles, 0, 0.0, nullptr, 0);
+}
+
+__global__ __launch_bounds__(512, 1) void k_syrk_update(const double* __restrict__ A, int64_t m, int n, int64_t lda,
+                                                        int tile_base, double alpha, double* __restrict__ W,
+                                                        int64_t ldw, const int32_t* __restrict__ info) {
+  if (info != nullptr && *info != 0) return;
+  syrk_tile_body<double, true>(A, m, n, lda, (m + kSyK - 1) / kSyK, nullptr, 0, tile_base, alpha, W, ldw);
 }
 
 // W(i, j), i >= j: the partial tiles summed in split order.
@@ -344,6 +382,16 @@ __global__ __launch_bounds__(256) void k_syrk_reduce(const double* __restrict__ 
   double v = 0.0;
   for (int s = 0; s < splits; ++s) v += part[(int64_t)s * ntiles * kSyTile + e];
   W[i + (int64_t)j * ldw] = v;
+}
+
+hipError_t launch_syrk_update(const double* A, int64_t m, int n, int64_t lda, double alpha, double* W, int64_t ldw,
+                              int skip_first_block_row, const int32_t* info, hipStream_t s) {
+  if (n <= 0 || m < 0) return hipSuccess;
+  const int base = skip_first_block_row ? 1 : 0;
+  const int tiles = syrk_ntiles(n) - base;
+  if (tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_syrk_update, dim3(tiles), dim3(512), 0, s, A, m, n, lda, base, alpha, W, ldw, info);
+  return hipGetLastError();
 }
 
 // Splits fill the device several times over (about 4096 workgroups, one per

@@ -207,7 +207,9 @@ def test_upper_product_wide_integer_exact(gpu_lib, n):
     assert np.array_equal(r, oracle.upper_product(r2, r1))
 
 
-@pytest.mark.parametrize("n,kappa", [(129, 1e2), (200, 1e3), (256, 1e3), (300, 1e2), (520, 1e2)])
+@pytest.mark.parametrize("n,kappa", [(129, 1e2), (200, 1e3), (256, 1e3), (300, 1e2),
+                                     # n >= 512: the 128-column blocked form on three streams; whole and ragged last blocks
+                                     (520, 1e2), (640, 1e3), (1000, 1e2), (1153, 1e4)])
 def test_cholinv_recursive_random_spd(gpu_lib, n, kappa):
     a = gdv_matrix(2 * n + 7, n, kappa, seed=n)
     w = oracle.syrk(a)
@@ -225,11 +227,12 @@ def test_cholinv_recursive_random_spd(gpu_lib, n, kappa):
     assert np.linalg.norm(r.T @ r - w) <= 10 * n * U64 * np.linalg.norm(w)
 
 
-@pytest.mark.parametrize("j", [3, 150, 255])
-def test_cholinv_recursive_breakdown(gpu_lib, j):
+@pytest.mark.parametrize("n,j", [(256, 3), (256, 150), (256, 255),
+                                 # blocked form: first block, a middle block, the ragged last block
+                                 (1000, 3), (1000, 500), (1000, 999)])
+def test_cholinv_recursive_breakdown(gpu_lib, n, j):
     import torch
-    n = 256
-    a = gdv_matrix(600, n, 10.0, seed=4)
+    a = gdv_matrix(2 * n + 88, n, 10.0, seed=4)
     w = oracle.syrk(a)
     w[j, :] = 0.0
     w[:, j] = 0.0
