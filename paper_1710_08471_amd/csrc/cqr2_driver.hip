@@ -1,8 +1,11 @@
 // Device-side drivers built from the kernels: the recursive CholInv of
-// Algorithm 2 for any n (base case: the single-workgroup kernel for n <= 128),
-// CholeskyQR2 (Algorithms 4 and 5) for n > 128 on the general GEMM, and the
-// least-squares solve on a finished factorization.
-// Everything is enqueued on one stream; nothing synchronizes with the host.
+// Algorithm 2 for any n (base case: the single-workgroup kernel for n <= 128;
+// from n = 512 the recursion split at 128 columns, run block by block with
+// look-ahead), CholeskyQR2 (Algorithms 4 and 5) for n > 128 on the tiled
+// kernels, and the least-squares solve on a finished factorization.
+// Everything is enqueued on the caller's stream, except the blocked CholInv's
+// bulk products, which fan out to two streams of the library and join back
+// through events; nothing synchronizes with the host.
 #include "cqr2_internal.h"
 
 #include <hip/hip_runtime.h>

@@ -131,6 +131,71 @@ def test_cholinv_split_at_128_matches_oracle(n):
     assert oracle.rel_fro(wrong, y.T) > 1e-3
 
 
+def _blocked_cholinv(w, b=128, drop_prev_diag=False):
+    """Algorithm 2 with the split at the first b columns at every level,
+    unrolled into a loop over b-column blocks in the order the GPU runs it for
+    n >= 512: base(k) on the diagonal block, the inverse's block column k from
+    the leading inverse, panel(k) = R_kk^-T W_{>k,k}^T, and update(k) in three
+    parts -- the next block column below its diagonal block, the trailing lower
+    triangle below block row k + 2, and the diagonal block k + 1 taking
+    update(k - 1) and update(k) together.  Only the lower triangle of the
+    working copy is read or updated."""
+    n = w.shape[0]
+    lw = np.tril(w).copy()
+    r = np.zeros((n, n))
+    ri = np.zeros((n, n))
+    nb = (n + b - 1) // b
+    c = [min(k * b, n) for k in range(nb + 3)]
+
+    def sub_lower(r0, c0, upd):
+        rows = np.arange(r0, r0 + upd.shape[0])[:, None]
+        cols = np.arange(c0, c0 + upd.shape[1])[None, :]
+        lw[r0:r0 + upd.shape[0], c0:c0 + upd.shape[1]] -= np.where(rows >= cols, upd, 0.0)
+
+    for k in range(nb):
+        c0, c1 = c[k], c[k + 1]
+        blk = np.tril(lw[c0:c1, c0:c1])
+        lkk, ykk = oracle.cholinv(blk + np.tril(blk, -1).T)
+        r[c0:c1, c0:c1], ri[c0:c1, c0:c1] = lkk.T, ykk.T
+        if k >= 1:
+            x = r[:c0, c0:c1] @ ri[c0:c1, c0:c1]
+            ri[:c0, c0:c1] = -(ri[:c0, :c0] @ x)
+        if c1 >= n:
+            break
+        c2, c3 = c[k + 2], c[k + 3]
+        r[c0:c1, c1:] = ri[c0:c1, c0:c1].T @ lw[c1:, c0:c1].T
+        sub_lower(c2, c1, r[c0:c1, c2:].T @ r[c0:c1, c1:c2])
+        if c3 < n:
+            sub_lower(c3, c2, r[c0:c1, c3:].T @ r[c0:c1, c2:])
+        kr = b if (k == 0 or drop_prev_diag) else 2 * b
+        rd = r[c1 - kr:c1, c1:c2]
+        sub_lower(c1, c1, rd.T @ rd)
+    return r, ri
+
+
+@pytest.mark.parametrize("n", [520, 640])
+def test_cholinv_blocked_lookahead_form_matches_oracle(n):
+    """The GPU's CholInv for n >= 512 is Algorithm 2 split at 128 columns at
+    every level, run block by block with look-ahead.  Written out with the
+    oracle's CholInv on the diagonal blocks, that schedule of block updates
+    reproduces the oracle's factor and inverse to rounding (every block of W
+    takes each step's update exactly once), and dropping update(k - 1) from the
+    diagonal block's combined update is caught."""
+    a = gdv_matrix(3 * n, n, 1e3, 500 + n)
+    w = oracle.syrk(a)
+    l, y = oracle.cholinv(w)
+    r, ri = _blocked_cholinv(w)
+    tol = 50 * n * U * np.linalg.cond(w)
+    assert oracle.rel_fro(r, l.T) <= tol
+    assert oracle.rel_fro(ri, y.T) <= tol
+    assert np.array_equal(r, np.triu(r)) and np.array_equal(ri, np.triu(ri))
+    try:
+        rb, _ = _blocked_cholinv(w, drop_prev_diag=True)
+        assert oracle.rel_fro(rb, l.T) > 1e-3
+    except oracle.NotSPD:
+        pass  # the mutant may also break down on a later block
+
+
 def test_cholinv_breakdown_columns():
     d = _gold("cholinv_exact_n8.json")
     w = np.array(d["W"])
