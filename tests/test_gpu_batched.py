@@ -24,6 +24,8 @@ MIX = [  # (m, n, kappa, seed): every n class, ragged m, chunk boundaries, one t
     # 128 < n <= 256 (eight-phase step): 2048-row chunks and a ragged tail, m = n, both blocks ragged
     (3000, 256, 1e5, 116), (2048 * 4 + 1, 129, 1e3, 117), (256, 256, 1e2, 118), (2047, 250, 1e6, 119),
     (6000, 300, 1e3, 120),
+    # n >= 512: the tiled path with the blocked look-ahead CholInv (helper streams) from a batched call
+    (3000, 600, 1e4, 121),
 ]
 
 

@@ -21,6 +21,7 @@ MIX = [
     (5000, 1, 1, 1.0, 701), (3000, 7, 0, 1e2, 702), (4096, 16, 3, 1e3, 703), (10000, 32, 0, 1e4, 704),
     (777, 33, 2, 1e3, 705), (20000, 64, 4, 1e6, 706), (9000, 100, 0, 1e5, 707), (8193, 128, 5, 1e6, 708),
     (5000, 200, 2, 1e4, 709), (3000, 300, 0, 1e3, 710), (64, 64, 1, 10.0, 711), (4000, 256, 3, 1e5, 712),
+    (3000, 520, 2, 1e3, 713),  # n >= 512: the blocked look-ahead CholInv inside a served solve
 ]
 
 
