@@ -62,11 +62,10 @@ static int rec_splits(int64_t M, int64_t N, int64_t K) { return gemm_pick_splits
 // update mode).  Stream C runs inv(k).  Each block of W takes every step's
 // update exactly once.  Events order every pair of steps that touch the same
 // block:
-//   B waits for panel(k) before its part of step k;
+//   B and C wait for panel(k) (recorded after base(k) and panel(k));
 //   the caller's stream waits for B's first part of step k - 1 before
-//   panel(k), and for its second part of step k - 2 before updating the
-//   diagonal block k + 1;
-//   C waits for base(k), which follows every panel that wrote R_{<k,k};
+//   panel(k); B's second part of step k - 2, which wrote the diagonal block
+//   k + 1 and block column k, comes before it on B;
 //   the caller's stream joins B and C at the end.
 // Used for n >= kLookaheadMinN at full inverse depth.
 constexpr int64_t kLookaheadMinN = 512;
@@ -193,37 +192,44 @@ static hipError_t cholinv_lookahead(double* W, int64_t ldw, int64_t n, double* R
   LookaheadStreams& L = g_la[dev];
   std::lock_guard<std::mutex> lock(L.mu);
   const int64_t nb = (n + kBaseN - 1) / kBaseN;
-  // events: D_k (base k done, k >= 1), P_k (panel k done), T1_k and T2_k
-  // (B's two parts of update k done), and the joins of B and C
-  CQR2_HIP(lookahead_events(L, (size_t)(4 * nb + 2)));
-  hipEvent_t* evD = L.ev.data();
-  hipEvent_t* evP = evD + nb;
+  // events: P_k (base(k), and panel(k) when there is one, done), T1_k (B's
+  // first part of update k done), and the joins of B and C.  Every event the
+  // caller's stream records or waits for costs the chain about 12 us, so the
+  // chain records one and waits for one per block.
+  CQR2_HIP(lookahead_events(L, (size_t)(2 * nb + 2)));
+  hipEvent_t* evP = L.ev.data();
   hipEvent_t* evT1 = evP + nb;
-  hipEvent_t* evT2 = evT1 + nb;
-  hipEvent_t joinB = evT2[nb], joinC = evT2[nb + 1];
+  hipEvent_t joinB = evT1[nb], joinC = evT1[nb + 1];
   const LookaheadLayout lay = lookahead_layout(n);
   double* wsA = (double*)(work + lay.a_ws);
   double* wsB = (double*)(work + lay.b_ws);
   double* X = (double*)(work + lay.c_x);
   double* wsC = (double*)(work + lay.c_ws);
-  auto blk = [&](int64_t k, int64_t& c0, int64_t& bk) {
-    c0 = k * kBaseN;
-    bk = n - c0 < kBaseN ? n - c0 : kBaseN;
-  };
   bool b_used = false, c_used = false;
   std::vector<char> has_b((size_t)nb, 0);  // step k ran work on B
   for (int64_t k = 0; k < nb; ++k) {
-    int64_t c0, bk;
-    blk(k, c0, bk);
+    const int64_t c0 = k * kBaseN, bk = n - c0 < kBaseN ? n - c0 : kBaseN;
     const int64_t c1 = c0 + bk, r1 = n - c1;
     double* Rkk = R + c0 + c0 * ldr;
     double* Rikk = Rinv + c0 + c0 * ldri;
     CQR2_HIP(launch_cholinv(W + c0 + c0 * ldw, ldw, (int)bk, Rkk, ldr, Rikk, ldri, nullptr, 0, info,
                             info_offset + (int)c0, s));
+    const int64_t b1 = r1 < kBaseN ? r1 : kBaseN, c2 = c1 + b1, r2 = n - c2;
+    double* Rk1 = R + c0 + c1 * ldr;  // R_{k,>k}: bk x r1
+    double* Rk2 = R + c0 + c2 * ldr;  // R_{k,>k+1}: bk x r2
+    if (r1 > 0) {
+      // panel(k) reads block column k below the diagonal, which B's first
+      // part of step k - 1 wrote last; B's second part of step k - 2, which
+      // wrote the diagonal block k + 1, precedes it on B
+      if (k >= 1 && has_b[k - 1]) CQR2_HIP(hipStreamWaitEvent(s, evT1[k - 1], 0));
+      // panel(k): R_{k,>k} = R_kk^-T W_{>k,k}^T
+      CQR2_HIP(launch_gemm(1, 1, bk, r1, bk, 1.0, Rikk, ldri, W + c1 + c0 * ldw, ldw, 0.0, Rk1, ldr, GEMM_A_LOWER,
+                           rec_splits(bk, r1, bk), wsA, info, s));
+    }
+    CQR2_HIP(hipEventRecord(evP[k], s));
     if (k >= 1) {
       // inv(k) on stream C: X = R_{<k,k} R_kk^-1, then R^-1_{<k,k} = -R^-1_{<k,<k} X
-      CQR2_HIP(hipEventRecord(evD[k], s));
-      CQR2_HIP(hipStreamWaitEvent(L.c, evD[k], 0));
+      CQR2_HIP(hipStreamWaitEvent(L.c, evP[k], 0));
       CQR2_HIP(launch_gemm(0, 0, c0, bk, bk, 1.0, R + c0 * ldr, ldr, Rikk, ldri, 0.0, X, c0, GEMM_B_UPPER,
                            rec_splits(c0, bk, bk), wsC, info, L.c));
       CQR2_HIP(launch_gemm(0, 0, c0, bk, c0, -1.0, Rinv, ldri, X, c0, 0.0, Rinv + c0 * ldri, ldri, GEMM_A_UPPER,
@@ -231,35 +237,23 @@ static hipError_t cholinv_lookahead(double* W, int64_t ldw, int64_t n, double* R
       c_used = true;
     }
     if (r1 <= 0) break;
-    const int64_t b1 = r1 < kBaseN ? r1 : kBaseN, c2 = c1 + b1, r2 = n - c2;
-    double* Rk1 = R + c0 + c1 * ldr;  // R_{k,>k}: bk x r1
-    double* Rk2 = R + c0 + c2 * ldr;  // R_{k,>k+1}: bk x r2
-    // panel(k) reads block column k below the diagonal, which B's first part
-    // of step k - 1 wrote last
-    if (k >= 1 && has_b[k - 1]) CQR2_HIP(hipStreamWaitEvent(s, evT1[k - 1], 0));
-    // panel(k): R_{k,>k} = R_kk^-T W_{>k,k}^T
-    CQR2_HIP(launch_gemm(1, 1, bk, r1, bk, 1.0, Rikk, ldri, W + c1 + c0 * ldw, ldw, 0.0, Rk1, ldr, GEMM_A_LOWER,
-                         rec_splits(bk, r1, bk), wsA, info, s));
     if (r2 > 0) {
       // on stream B, update(k) below block row k + 1: first block column
       // k + 1 (the next panel's input), then the trailing lower triangle
       // below block row k + 2 in one launch of the tiled SYRK in update mode
       // (the diagonal block k + 2 takes update(k) on the caller's stream,
       // together with update(k + 1))
-      CQR2_HIP(hipEventRecord(evP[k], s));
       CQR2_HIP(hipStreamWaitEvent(L.b, evP[k], 0));
       CQR2_HIP(launch_gemm(1, 0, r2, b1, bk, -1.0, Rk2, ldr, Rk1, ldr, 1.0, W + c2 + c1 * ldw, ldw, 0,
                            rec_splits(r2, b1, bk), wsB, info, L.b));
       CQR2_HIP(hipEventRecord(evT1[k], L.b));
       CQR2_HIP(launch_syrk_update(Rk2, bk, (int)r2, ldr, -1.0, W + c2 + c2 * ldw, ldw, 1, info, L.b));
-      CQR2_HIP(hipEventRecord(evT2[k], L.b));
       has_b[k] = 1;
       b_used = true;
     }
     // the diagonal block k + 1, the next link of the chain, takes update(k)
     // and update(k - 1) in one product (block rows k - 1 and k of R are
-    // adjacent); B's second part of step k - 2 wrote the block before
-    if (k >= 2 && has_b[k - 2]) CQR2_HIP(hipStreamWaitEvent(s, evT2[k - 2], 0));
+    // adjacent)
     const int64_t kr = k >= 1 ? 2 * kBaseN : bk;
     double* Rd = R + (c1 - kr) + c1 * ldr;
     CQR2_HIP(launch_gemm(1, 0, b1, b1, kr, -1.0, Rd, ldr, Rd, ldr, 1.0, W + c1 + c1 * ldw, ldw, GEMM_C_LOWER,
