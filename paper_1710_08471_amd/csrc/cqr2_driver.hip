@@ -71,25 +71,19 @@ static int rec_splits(int64_t M, int64_t N, int64_t K) { return gemm_pick_splits
 constexpr int64_t kLookaheadMinN = 512;
 
 struct LookaheadLayout {
-  size_t a_ws, b_ws, c_x, c_ws, total;  // offsets of the three streams' scratch, and the total
+  size_t b_ws, c_x, c_ws, total;  // offsets of the helper streams' scratch, and the total
 };
 
 static size_t la_align(size_t x) { return (x + 255) / 256 * 256; }
 
-// Reduction splits of the chain's small products (128 x 128 x 128): the
-// split product and its sum finish sooner than four long-K workgroups.
-static int la_splits_a(int64_t M, int64_t N, int64_t K) { return rec_splits(M, N, K); }
 
 static LookaheadLayout lookahead_layout(int64_t n) {
-  size_t a = 0, b = 0, cx = 0, cw = 0;
+  size_t b = 0, cx = 0, cw = 0;
   auto mx = [](size_t& v, size_t x) { v = x > v ? x : v; };
   for (int64_t c0 = 0; c0 < n; c0 += kBaseN) {
     const int64_t bk = n - c0 < kBaseN ? n - c0 : kBaseN, c1 = c0 + bk, r1 = n - c1;
     if (r1 > 0) {
       const int64_t b1 = r1 < kBaseN ? r1 : kBaseN, r2 = r1 - b1;
-      mx(a, gemm_workspace_bytes(bk, r1, rec_splits(bk, r1, bk)));
-      mx(a, gemm_workspace_bytes(b1, b1, la_splits_a(b1, b1, 2 * kBaseN)));
-      mx(a, gemm_workspace_bytes(b1, b1, la_splits_a(b1, b1, bk)));
       if (r2 > 0) mx(b, gemm_workspace_bytes(r2, b1, rec_splits(r2, b1, bk)));
     }
     if (c0 > 0) {
@@ -99,8 +93,7 @@ static LookaheadLayout lookahead_layout(int64_t n) {
     }
   }
   LookaheadLayout L{};
-  L.a_ws = 0;
-  L.b_ws = la_align(a);
+  L.b_ws = 0;
   L.c_x = L.b_ws + la_align(b);
   L.c_ws = L.c_x + la_align(cx);
   L.total = L.c_ws + la_align(cw);
@@ -184,6 +177,119 @@ static hipError_t lookahead_events(LookaheadStreams& L, size_t count) {
   return hipSuccess;
 }
 
+// ---- The chain's two small products ------------------------------------------
+// MFMA 16x16x4 (FP64) with both operands read straight from global memory (a
+// few hundred KB, just written): no LDS staging, the whole reduction in one
+// launch.  Operand lane l holds A(row l%16, k + l/16) and B(k + l/16, column
+// l%16); result entry r of lane l is D(4r + l/16, l%16).  The operands of up
+// to kChainBatch k-steps are loaded before their products.
+typedef double chain_d4 __attribute__((ext_vector_type(4)));
+constexpr int kChainBatch = 32;
+
+// acc += sum over k in [kb, ke) of opA(i, k) opB(k, j) for this lane's i, j;
+// ld(k, row) loads opA or opB (0 outside).
+template <typename LA, typename LB>
+__device__ __forceinline__ chain_d4 chain_mfma(int kb, int ke, int k4, LA lda_, LB ldb_) {
+  chain_d4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int k0 = kb; k0 < ke; k0 += 4 * kChainBatch) {
+    double a[kChainBatch], b[kChainBatch];
+#pragma unroll
+    for (int q = 0; q < kChainBatch; ++q) {
+      const int k = k0 + 4 * q + k4;
+      a[q] = k < ke ? lda_(k) : 0.0;
+      b[q] = k < ke ? ldb_(k) : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < kChainBatch; ++q)
+      if (k0 + 4 * q < ke) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], b[q], acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+// Out(j, i) = sum_{k < K, k <= j} A(i, k) U(k, j) for i < M, j < N (A: M x K,
+// lda; U: K x N upper, ldb, zero below its diagonal), stored transposed:
+// Out(j, i) at C[j + i ldc].  One wave per 16 x 16 tile, four per workgroup.
+__global__ __launch_bounds__(256) void k_chain_panel(const double* __restrict__ A, int64_t lda,
+                                                     const double* __restrict__ U, int64_t ldb, int M, int N, int K,
+                                                     double* __restrict__ C, int64_t ldc,
+                                                     const int32_t* __restrict__ info) {
+  if (info != nullptr && *info != 0) return;
+  const int lane = threadIdx.x & 63;
+  const int t = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+  const int tn = (N + 15) / 16, I = t / tn, J = t % tn;
+  if (16 * I >= M) return;  // past the last tile (wave-uniform; no barrier follows)
+  const int r16 = lane & 15, k4 = lane >> 4;
+  const int i = 16 * I + r16, j = 16 * J + r16;
+  const int ke = K < 16 * J + 16 ? K : 16 * J + 16;  // U(k, j) = 0 for k > j
+  const chain_d4 acc = chain_mfma(
+      0, ke, k4, [&](int k) { return i < M ? A[i + (int64_t)k * lda] : 0.0; },
+      [&](int k) { return j < N ? U[k + (int64_t)j * ldb] : 0.0; });
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int ii = 16 * I + 4 * r + k4, jj = 16 * J + r16;
+    if (ii < M && jj < N) C[jj + (int64_t)ii * ldc] = acc[r];
+  }
+}
+
+// C(i, j) -= sum_{k < K} A(k, i) A(k, j) for j <= i < M (A: K x M, lda; C: the
+// lower triangle of M x M).  A workgroup per lower 16 x 16 tile; its four
+// waves take a quarter of the reduction each, and wave 0 adds the four in
+// wave order.
+__global__ __launch_bounds__(256) void k_chain_diag(const double* __restrict__ A, int64_t lda, int M, int K,
+                                                    double* __restrict__ C, int64_t ldc,
+                                                    const int32_t* __restrict__ info) {
+  __shared__ double part[4][4][64];
+  if (info != nullptr && *info != 0) return;
+  const int t = (int)blockIdx.x;
+  int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while (I * (I + 1) / 2 > t) --I;
+  while ((I + 1) * (I + 2) / 2 <= t) ++I;
+  const int J = t - I * (I + 1) / 2;
+  const int w = (int)(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int r16 = lane & 15, k4 = lane >> 4;
+  const int i = 16 * I + r16, j = 16 * J + r16;
+  const int kq = (K + 15) / 16 * 4;  // each wave's share, a multiple of 4
+  const int kb = w * kq, ke = K < kb + kq ? K : kb + kq;
+  const chain_d4 acc = chain_mfma(
+      kb, ke, k4, [&](int k) { return i < M ? A[k + (int64_t)i * lda] : 0.0; },
+      [&](int k) { return j < M ? A[k + (int64_t)j * lda] : 0.0; });
+#pragma unroll
+  for (int r = 0; r < 4; ++r) part[w][r][lane] = acc[r];
+  __syncthreads();
+  if (w != 0) return;
+  double old[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int ii = 16 * I + 4 * r + k4, jj = 16 * J + r16;
+    old[r] = (ii < M && jj <= ii) ? C[ii + (int64_t)jj * ldc] : 0.0;
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int ii = 16 * I + 4 * r + k4, jj = 16 * J + r16;
+    const double sum = ((part[0][r][lane] + part[1][r][lane]) + part[2][r][lane]) + part[3][r][lane];
+    if (ii < M && jj <= ii) C[ii + (int64_t)jj * ldc] = old[r] - sum;
+  }
+}
+
+// R_{k,>k} = R_kk^-T W_{>k,k}^T, computed as (W_{>k,k} R_kk^-1)ᵀ: Wb is the
+// r1 x bk block W_{>k,k} (ldw), Rikk the bk x bk upper R_kk^-1 (ldri), Rk1 the
+// bk x r1 block of R (ldr).
+static hipError_t launch_chain_panel(const double* Wb, int64_t ldw, const double* Rikk, int64_t ldri, int64_t r1,
+                                     int64_t bk, double* Rk1, int64_t ldr, const int32_t* info, hipStream_t s) {
+  const int64_t tiles = ((r1 + 15) / 16) * ((bk + 15) / 16);
+  hipLaunchKernelGGL(k_chain_panel, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, s, Wb, ldw, Rikk, ldri,
+                     (int)r1, (int)bk, (int)bk, Rk1, ldr, info);
+  return hipGetLastError();
+}
+
+// W_d (n1 x n1, lower) -= Rdᵀ Rd for the kr x n1 block Rd of R (ldr).
+static hipError_t launch_chain_diag(const double* Rd, int64_t ldr, int64_t kr, int64_t n1, double* Wd, int64_t ldw,
+                                    const int32_t* info, hipStream_t s) {
+  const int64_t t = (n1 + 15) / 16, tiles = t * (t + 1) / 2;
+  hipLaunchKernelGGL(k_chain_diag, dim3((unsigned)tiles), dim3(256), 0, s, Rd, ldr, (int)n1, (int)kr, Wd, ldw, info);
+  return hipGetLastError();
+}
+
 static hipError_t cholinv_lookahead(double* W, int64_t ldw, int64_t n, double* R, int64_t ldr, double* Rinv,
                                     int64_t ldri, char* work, int32_t* info, int info_offset, hipStream_t s) {
   int dev = 0;
@@ -201,7 +307,6 @@ static hipError_t cholinv_lookahead(double* W, int64_t ldw, int64_t n, double* R
   hipEvent_t* evT1 = evP + nb;
   hipEvent_t joinB = evT1[nb], joinC = evT1[nb + 1];
   const LookaheadLayout lay = lookahead_layout(n);
-  double* wsA = (double*)(work + lay.a_ws);
   double* wsB = (double*)(work + lay.b_ws);
   double* X = (double*)(work + lay.c_x);
   double* wsC = (double*)(work + lay.c_ws);
@@ -223,8 +328,7 @@ static hipError_t cholinv_lookahead(double* W, int64_t ldw, int64_t n, double* R
       // wrote the diagonal block k + 1, precedes it on B
       if (k >= 1 && has_b[k - 1]) CQR2_HIP(hipStreamWaitEvent(s, evT1[k - 1], 0));
       // panel(k): R_{k,>k} = R_kk^-T W_{>k,k}^T
-      CQR2_HIP(launch_gemm(1, 1, bk, r1, bk, 1.0, Rikk, ldri, W + c1 + c0 * ldw, ldw, 0.0, Rk1, ldr, GEMM_A_LOWER,
-                           rec_splits(bk, r1, bk), wsA, info, s));
+      CQR2_HIP(launch_chain_panel(W + c1 + c0 * ldw, ldw, Rikk, ldri, r1, bk, Rk1, ldr, info, s));
     }
     CQR2_HIP(hipEventRecord(evP[k], s));
     if (k >= 1) {
@@ -255,9 +359,7 @@ static hipError_t cholinv_lookahead(double* W, int64_t ldw, int64_t n, double* R
     // and update(k - 1) in one product (block rows k - 1 and k of R are
     // adjacent)
     const int64_t kr = k >= 1 ? 2 * kBaseN : bk;
-    double* Rd = R + (c1 - kr) + c1 * ldr;
-    CQR2_HIP(launch_gemm(1, 0, b1, b1, kr, -1.0, Rd, ldr, Rd, ldr, 1.0, W + c1 + c1 * ldw, ldw, GEMM_C_LOWER,
-                         la_splits_a(b1, b1, kr), wsA, info, s));
+    CQR2_HIP(launch_chain_diag(R + (c1 - kr) + c1 * ldr, ldr, kr, b1, W + c1 + c1 * ldw, ldw, info, s));
   }
   if (b_used) {
     CQR2_HIP(hipEventRecord(joinB, L.b));
