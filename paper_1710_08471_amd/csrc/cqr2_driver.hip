@@ -77,6 +77,16 @@ struct LookaheadLayout {
 static size_t la_align(size_t x) { return (x + 255) / 256 * 256; }
 
 
+// Reduction splits of inv(k)'s long product R^-1_{<k,<k} X (c0 x bk x c0): at
+// most 256 of the reduction per workgroup, since the chain does not wait for
+// it and its last steps would otherwise run past the chain.
+static int la_inv_splits(int64_t c0, int64_t bk) {
+  const int s = rec_splits(c0, bk, c0);
+  int64_t by_len = (c0 + 255) / 256;
+  if (by_len > 16) by_len = 16;
+  return by_len > s ? (int)by_len : s;
+}
+
 static LookaheadLayout lookahead_layout(int64_t n) {
   size_t b = 0, cx = 0, cw = 0;
   auto mx = [](size_t& v, size_t x) { v = x > v ? x : v; };
@@ -89,7 +99,7 @@ static LookaheadLayout lookahead_layout(int64_t n) {
     if (c0 > 0) {
       mx(cx, (size_t)c0 * bk * sizeof(double));
       mx(cw, gemm_workspace_bytes(c0, bk, rec_splits(c0, bk, bk)));
-      mx(cw, gemm_workspace_bytes(c0, bk, rec_splits(c0, bk, c0)));
+      mx(cw, gemm_workspace_bytes(c0, bk, la_inv_splits(c0, bk)));
     }
   }
   LookaheadLayout L{};
@@ -337,7 +347,7 @@ static hipError_t cholinv_lookahead(double* W, int64_t ldw, int64_t n, double* R
       CQR2_HIP(launch_gemm(0, 0, c0, bk, bk, 1.0, R + c0 * ldr, ldr, Rikk, ldri, 0.0, X, c0, GEMM_B_UPPER,
                            rec_splits(c0, bk, bk), wsC, info, L.c));
       CQR2_HIP(launch_gemm(0, 0, c0, bk, c0, -1.0, Rinv, ldri, X, c0, 0.0, Rinv + c0 * ldri, ldri, GEMM_A_UPPER,
-                           rec_splits(c0, bk, c0), wsC, info, L.c));
+                           la_inv_splits(c0, bk), wsC, info, L.c));
       c_used = true;
     }
     if (r1 <= 0) break;
