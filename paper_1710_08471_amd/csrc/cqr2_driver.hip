@@ -606,7 +606,10 @@ GeneralPlan plan_general(int64_t m, int64_t n, bool mixed, int depth) {
   // the Gram's partials (FP64 or FP32 input alike)
   const size_t gws = n <= kWideMaxN ? plan_gram_wide(m, n).partial_bytes : plan_syrk(m, n).partial_bytes;
   const size_t rws = cholinv_rec_workspace(n);
-  p.off_scratch = take(gws > rws ? gws : rws);
+  const size_t uws = n <= kWideMaxN ? 0 : upper_seg_partial_bytes(n);  // R = R2 R1's partial tiles
+  size_t sws = gws > rws ? gws : rws;
+  sws = sws > uws ? sws : uws;
+  p.off_scratch = take(sws);
   p.off_q1 = take((size_t)m * n * (mixed ? sizeof(float) : sizeof(double)));
   if (depth > 0) {
     Block blk[256];
@@ -704,9 +707,14 @@ hipError_t factor_general(const double* A, int64_t m, int64_t n, int64_t lda, do
   th.end(4, s);
   constexpr int kUp = GEMM_A_UPPER | GEMM_B_UPPER | GEMM_C_UPPER;
   if (!shifted) {
-    // R = R2 R1
+    // R = R2 R1 (n > 256: the segmented tall kernel on R1's upper image)
     th.begin(5, s);
-    CQR2_HIP(launch_gemm(0, 0, n, n, n, 1.0, R2, n, R1, n, 0.0, P, n, kUp, 1, nullptr, info, s));
+    if (wide) {
+      CQR2_HIP(launch_gemm(0, 0, n, n, n, 1.0, R2, n, R1, n, 0.0, P, n, kUp, 1, nullptr, info, s));
+    } else {
+      CQR2_HIP(launch_upper_image(R1, n, (int)n, Uimg, s));
+      CQR2_HIP(launch_upper_seg(R2, (int)n, n, Uimg, P, n, (double*)scratch, info, s));
+    }
     CQR2_HIP(launch_finalize_r(P, n, R, ldr, n, info, d_info, s));
     th.end(5, s);
     return hipSuccess;

@@ -148,6 +148,13 @@ inline size_t upper_image_bytes(int64_t n) {
   return ld * ld * sizeof(double);
 }
 hipError_t launch_upper_image(const double* X, int64_t ldx, int n, double* T, hipStream_t s);
+// R = X Y for upper-triangular X, Y (n x n): X column-major (ldx, exact zeros
+// below its diagonal), Y as its upper image (launch_upper_image).  Writes R's
+// upper triangle (entries below the diagonal are left alone or written as 0);
+// part: upper_seg_partial_bytes(n) of scratch.
+size_t upper_seg_partial_bytes(int64_t n);
+hipError_t launch_upper_seg(const double* X, int n, int64_t ldx, const double* Yimg, double* R, int64_t ldr,
+                            double* part, const int32_t* info, hipStream_t s);
 // Q = A U (U given as its upper image); A FP64 or FP32 (a_f32), FP64
 // arithmetic.  Reads rows of A across 256-column tiles: not in place for n > 256.
 hipError_t launch_tall_gemm(int a_f32, const void* A, int64_t m, int n, int64_t lda, const double* Uimg, double* Q,

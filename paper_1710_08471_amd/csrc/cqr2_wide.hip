@@ -639,6 +639,251 @@ __global__ __launch_bounds__(512, 1) void k_tall(const TA* __restrict__ A, int64
   }
 }
 
+// ============================================================================
+// R = X Y for upper-triangular X, Y (n x n): the tall kernel's 128 x 256 tiles
+// and chunk pipeline, with X column-major (ldx, zero below its diagonal) as A
+// and Y as its zero-padded row-major image.  A tile (I, J) reduces over
+// k in [128 I, min(n, 256 (J + 1))) only; that range is cut into segments of
+// at most kSegChunks 16-wide chunks so that the far-corner tiles (whole-n
+// reductions) spread over several workgroups.  Work items run over the tiles
+// in row-major order, each tile's segments in turn; a tile with one segment
+// writes R directly, the others write partial tiles that k_upper_seg_reduce
+// adds in segment order.  Tiles wholly below the diagonal are skipped (R's
+// lower triangle is left to the caller).
+// ============================================================================
+constexpr int kSegChunks = 64;  // 1024 of the reduction (measured: 16 to 256 chunks, 64 fastest at n = 4096)
+
+struct SegItem {
+  int I, J, cb, ce;  // tile and chunk range
+  int slot;          // partial slot, or -1 for a one-segment tile
+};
+
+// the work item `item` of the order above (or I = -1 past the last)
+__device__ __host__ inline SegItem seg_item(int n, int item) {
+  const int TI = (n + kTallRows - 1) / kTallRows, TJ = (n + kTallUld - 1) / kTallUld;
+  int slot = 0;
+  for (int I = 0; I < TI; ++I)
+    for (int J = 0; J < TJ; ++J) {
+      const int kend = n < kTallUld * (J + 1) ? n : kTallUld * (J + 1);
+      const int cb = (kTallRows * I) / kTallK, ce = (kend + kTallK - 1) / kTallK;
+      if (ce <= cb) continue;
+      const int nseg = (ce - cb + kSegChunks - 1) / kSegChunks;
+      if (item < nseg) {
+        const int b = cb + item * kSegChunks, e = b + kSegChunks < ce ? b + kSegChunks : ce;
+        return SegItem{I, J, b, e, nseg > 1 ? slot + item : -1};
+      }
+      item -= nseg;
+      if (nseg > 1) slot += nseg;
+    }
+  return SegItem{-1, -1, 0, 0, -1};
+}
+
+__global__ __launch_bounds__(512, 1) void k_upper_seg(const double* __restrict__ X, int n, int64_t ldx,
+                                                      const double* __restrict__ Y, int64_t ldy,
+                                                      double* __restrict__ R, int64_t ldr,
+                                                      double* __restrict__ part, const int32_t* __restrict__ info) {
+  constexpr int kABytes = kTallK * kTallRows * 8;
+  constexpr int kUBytes = kTallK * kTallUld * 8;
+  constexpr int kBufBytes = kABytes + kUBytes;
+  constexpr int kPerChunk = 2 + 4;  // per wave and chunk: two 1 KB X columns, four 1 KB halves of Y rows
+  __shared__ __attribute__((aligned(16))) char smem[kTallBufs * kBufBytes];
+  if (info != nullptr && *info != 0) return;
+  const SegItem it = seg_item(n, (int)blockIdx.x);
+  if (it.I < 0) return;
+  const int64_t i0 = (int64_t)it.I * kTallRows;
+  const int j0 = it.J * kTallUld;
+  const int count = it.ce - it.cb;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wr = 64 * (wave >> 2), wc = j0 + tall_wave_col0(wave);
+  const bool direct = (i0 + kTallRows <= n) && (((uintptr_t)X & 15u) == 0) && (((ldx * 8) & 15) == 0);
+  auto abuf = [&](int b) { return (double*)(smem + b * kBufBytes); };
+  auto ubuf = [&](int b) { return (double*)(smem + b * kBufBytes + kABytes); };
+  // chunk c of this item (absolute chunk it.cb + c) into buffer c % kTallBufs;
+  // columns of X past n are read from column n - 1 (times zero rows of Y)
+  auto issue = [&](int c) {
+    const int b = c % kTallBufs;
+    const int k0 = (it.cb + c) * kTallK;
+    double* As = abuf(b);
+    if (direct) {
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int kc = 2 * wave + t;
+        const int col = k0 + kc < n ? k0 + kc : n - 1;
+        __builtin_amdgcn_global_load_lds((const void*)(X + i0 + 2 * lane + (int64_t)col * ldx),
+                                         (__attribute__((address_space(3))) void*)(As + kc * kTallRows), 16, 0, 0);
+      }
+    } else {
+      for (int e = tid; e < kTallK * kTallRows; e += 512) {
+        const int r = e % kTallRows, kc = e / kTallRows;
+        const int64_t gi = i0 + r;
+        const int col = k0 + kc < n ? k0 + kc : n - 1;
+        As[kc * kTallRows + r] = gi < n ? X[gi + (int64_t)col * ldx] : 0.0;
+      }
+    }
+    double* Us = ubuf(b);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int h = 4 * wave + t;
+      const int kr = h >> 1, c0 = 128 * (h & 1);
+      __builtin_amdgcn_global_load_lds((const void*)(Y + (int64_t)(k0 + kr) * ldy + j0 + c0 + 2 * lane),
+                                       (__attribute__((address_space(3))) void*)(Us + kr * kTallUld + c0), 16, 0, 0);
+    }
+  };
+  for (int e = tid; e < kTallBufs * kBufBytes / 8; e += 512) ((double*)smem)[e] = 0.0;
+  lds_barrier();
+
+  double acc[4][16];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 16; ++b) acc[a][b] = 0.0;
+  issue(0);
+  if (count > 1) issue(1);
+  const int ar = lane & 15, ak = lane >> 4, bc = lane & 3;
+  for (int c = 0; c < count; ++c) {
+    if (direct && c + 1 < count) wait_vmcnt<kPerChunk>();
+    else wait_vmcnt<0>();
+    lds_barrier();
+    if (c + 2 < count) issue(c + 2);
+    const double* As = abuf(c % kTallBufs);
+    const double* Us = ubuf(c % kTallBufs);
+    const int k0 = (it.cb + c) * kTallK;
+    if (wc + 63 >= k0 && wc < n) {
+#pragma unroll
+      for (int ks = 0; ks < kTallK; ks += 4) {
+        const int kk = ks + ak;
+        double a[4];
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) a[rt] = As[kk * kTallRows + wr + 16 * rt + ar];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {  // Y(k, j) = 0 for every k > j
+          if (wc + 16 * q + 15 >= k0 + ks) {
+            double b[4];
+#pragma unroll
+            for (int c4 = 0; c4 < 4; ++c4) b[c4] = Us[kk * kTallUld + (wc - j0) + 16 * q + 4 * c4 + bc];
+#pragma unroll
+            for (int c4 = 0; c4 < 4; ++c4)
+#pragma unroll
+              for (int rt = 0; rt < 4; ++rt)
+                acc[rt][4 * q + c4] = __builtin_amdgcn_mfma_f64_4x4x4f64(a[rt], b[c4], acc[rt][4 * q + c4], 0, 0, 0);
+          }
+        }
+      }
+    }
+  }
+  // output lane l: (r0 + 4 ((l >> 2) & 3) + (l >> 4), c0 + (l & 3)); a partial tile is
+  // 128 x 256 column-major (ld 128)
+  double* out = it.slot < 0 ? R + i0 + (int64_t)j0 * ldr : part + (int64_t)it.slot * kTallRows * kTallUld;
+  const int64_t ldo = it.slot < 0 ? ldr : kTallRows;
+  const int orow = 4 * ((lane >> 2) & 3) + (lane >> 4), ocol = lane & 3;
+#pragma unroll
+  for (int rt = 0; rt < 4; ++rt) {
+    const int ri = wr + 16 * rt + orow;
+    if (i0 + ri >= n) continue;
+#pragma unroll
+    for (int cg = 0; cg < 16; ++cg) {
+      const int cj = wc - j0 + 4 * cg + ocol;
+      if (j0 + cj < n) out[ri + (int64_t)cj * ldo] = acc[rt][cg];
+    }
+  }
+}
+
+// The t-th tile with several segments (row-major order): its tile, first
+// partial slot and segment count (I = -1 past the last).
+__device__ inline void seg_multi_tile(int n, int t, int& I_, int& J_, int& slot_, int& nseg_) {
+  const int TI = (n + kTallRows - 1) / kTallRows, TJ = (n + kTallUld - 1) / kTallUld;
+  int slot = 0;
+  I_ = -1;
+  for (int I = 0; I < TI; ++I)
+    for (int J = 0; J < TJ; ++J) {
+      const int kend = n < kTallUld * (J + 1) ? n : kTallUld * (J + 1);
+      const int cb = (kTallRows * I) / kTallK, ce = (kend + kTallK - 1) / kTallK;
+      if (ce <= cb) continue;
+      const int nseg = (ce - cb + kSegChunks - 1) / kSegChunks;
+      if (nseg <= 1) continue;
+      if (t == 0) {
+        I_ = I, J_ = J, slot_ = slot, nseg_ = nseg;
+        return;
+      }
+      --t;
+      slot += nseg;
+    }
+}
+
+// R tiles with several segments: their partial tiles added in segment order,
+// kSegReduceWGs workgroups per tile (blockIdx.y: the piece), the loads of all
+// segments of an entry issued before the sum.
+constexpr int kSegReduceWGs = 4;
+constexpr int kSegMaxParts = (4096 / kTallK + kSegChunks - 1) / kSegChunks;  // segments of a 4096-long reduction
+
+__global__ __launch_bounds__(256) void k_upper_seg_reduce(int n, double* __restrict__ R, int64_t ldr,
+                                                          const double* __restrict__ part,
+                                                          const int32_t* __restrict__ info) {
+  if (info != nullptr && *info != 0) return;
+  int I, J, slot, nseg;
+  seg_multi_tile(n, (int)blockIdx.x, I, J, slot, nseg);
+  if (I < 0) return;
+  const double* p0 = part + (int64_t)slot * kTallRows * kTallUld;
+  constexpr int kPiece = kTallRows * kTallUld / kSegReduceWGs;
+  for (int e = (int)blockIdx.y * kPiece + (int)threadIdx.x; e < ((int)blockIdx.y + 1) * kPiece; e += 256) {
+    const int ri = e % kTallRows, cj = e / kTallRows;
+    const int64_t i = (int64_t)I * kTallRows + ri, j = (int64_t)J * kTallUld + cj;
+    if (i >= n || j >= n) continue;
+    double v = 0.0;
+    for (int s0 = 0; s0 < nseg; s0 += kSegMaxParts) {
+      double x[kSegMaxParts];
+#pragma unroll
+      for (int q = 0; q < kSegMaxParts; ++q)
+        x[q] = s0 + q < nseg ? p0[(int64_t)(s0 + q) * kTallRows * kTallUld + e] : 0.0;
+#pragma unroll
+      for (int q = 0; q < kSegMaxParts; ++q)
+        if (s0 + q < nseg) v += x[q];
+    }
+    R[i + j * ldr] = v;
+  }
+}
+
+// Items, partial slots and multi-segment tiles of the segmented product (the
+// host side of seg_item).
+static void upper_seg_plan(int n, int* items, int* slots, int* multi) {
+  const int TI = (n + kTallRows - 1) / kTallRows, TJ = (n + kTallUld - 1) / kTallUld;
+  int it = 0, sl = 0, mt = 0;
+  for (int I = 0; I < TI; ++I)
+    for (int J = 0; J < TJ; ++J) {
+      const int kend = n < kTallUld * (J + 1) ? n : kTallUld * (J + 1);
+      const int cb = (kTallRows * I) / kTallK, ce = (kend + kTallK - 1) / kTallK;
+      if (ce <= cb) continue;
+      const int nseg = (ce - cb + kSegChunks - 1) / kSegChunks;
+      it += nseg;
+      if (nseg > 1) sl += nseg, ++mt;
+    }
+  *items = it;
+  *slots = sl;
+  *multi = mt;
+}
+
+size_t upper_seg_partial_bytes(int64_t n) {
+  int items = 0, slots = 0, multi = 0;
+  upper_seg_plan((int)n, &items, &slots, &multi);
+  return (size_t)slots * kTallRows * kTallUld * sizeof(double);
+}
+
+hipError_t launch_upper_seg(const double* X, int n, int64_t ldx, const double* Yimg, double* R, int64_t ldr,
+                            double* part, const int32_t* info, hipStream_t s) {
+  int items = 0, slots = 0, multi = 0;
+  upper_seg_plan(n, &items, &slots, &multi);
+  if (items <= 0) return hipSuccess;
+  if (slots > 0 && part == nullptr) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_upper_seg, dim3((unsigned)items), dim3(512), 0, s, X, n, ldx, Yimg, upper_image_ld(n), R, ldr,
+                     part, info);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || multi == 0) return e;
+  hipLaunchKernelGGL(k_upper_seg_reduce, dim3((unsigned)multi, kSegReduceWGs), dim3(256), 0, s, n, R, ldr, part,
+                     info);
+  return hipGetLastError();
+}
+
 // Row-major, zero-padded image of the upper triangle of an n x n column-major
 // X (ldx): T[ldt k + j] = X(k, j) for k <= j < n, else 0, for k, j < ldt
 // (ldt = n rounded up to 256).

@@ -231,7 +231,9 @@ def test_factor_integer_orthogonal_columns_exact(gpu_lib):
 
 @pytest.mark.parametrize("m,n,kappa,seed", [
     (2000, 129, 1e3, 31), (10000, 200, 1e5, 32), (30000, 256, 1e6, 33), (1500, 300, 1e4, 34),
-    (256, 256, 1e2, 35), (4096, 520, 1e3, 36)])
+    (256, 256, 1e2, 35), (4096, 520, 1e3, 36),
+    # n > 1024: R = R2 R1's far-corner tiles take several reduction segments and their sum
+    (2500, 1200, 1e3, 37)])
 def test_factor_wide_matches_oracle(gpu_lib, m, n, kappa, seed):
     a = gdv_matrix(m, n, kappa, seed)
     q_ref, r_ref = oracle.cqr2(a)
@@ -249,8 +251,9 @@ def test_factor_wide_breakdown(gpu_lib):
     assert np.all(np.isnan(to_host(r)))
 
 
-def test_factor_wide_deterministic(gpu_lib):
-    a = gdv_matrix(20000, 256, 1e4, 38)
+@pytest.mark.parametrize("m,n", [(20000, 256), (3000, 1200)])  # 1200: the blocked CholInv on three streams
+def test_factor_wide_deterministic(gpu_lib, m, n):
+    a = gdv_matrix(m, n, 1e4, 38)
     ad = to_dev(a)
     q1, r1 = gpu_lib.factor(ad)
     q2, r2 = gpu_lib.factor(ad)
