@@ -11,7 +11,14 @@
 // and, for any n > 256, the Gram by 128 x 256 tiles of its lower triangle:
 //   k_syrk_tile     partial tiles over row splits, MFMA 4x4x4 fed the way
 //                   k_tall is fed;
-//   k_syrk_reduce   fixed-order sum of the partial tiles into W (lower).
+//   k_syrk_reduce   fixed-order sum of the partial tiles into W (lower);
+//   k_syrk_update   the same tiles with the whole (short) reduction in one
+//                   workgroup, added into W (the blocked CholInv's trailing
+//                   update);
+// and R = R2 R1 for n > 256:
+//   k_upper_seg     k_tall's tiles on R2 and R1's upper image, each tile's
+//                   reduction cut into segments;
+//   k_upper_seg_reduce  fixed-order sum of a tile's segments.
 #include "cqr2_internal.h"
 
 #include <hip/hip_runtime.h>
