@@ -216,13 +216,17 @@ __device__ __forceinline__ chain_d4 chain_mfma(int kb, int ke, int k4, LA lda_, 
   return acc;
 }
 
-// Out(j, i) = sum_{k < K, k <= j} A(i, k) U(k, j) for i < M, j < N (A: M x K,
-// lda; U: K x N upper, ldb, zero below its diagonal), stored transposed:
-// Out(j, i) at C[j + i ldc].  One wave per 16 x 16 tile, four per workgroup.
-__global__ __launch_bounds__(256) void k_chain_panel(const double* __restrict__ A, int64_t lda,
-                                                     const double* __restrict__ U, int64_t ldb, int M, int N, int K,
-                                                     double* __restrict__ C, int64_t ldc,
-                                                     const int32_t* __restrict__ info) {
+// D = alpha A B for A (M x K, lda) and B (K x N, ldb), both column-major:
+// A upper (A(i, k) = 0 for k < i) if AUP, B upper (B(k, j) = 0 for k > j) if
+// BUP -- the reduction of a tile then skips those k, and the entries it still
+// reads inside a 16 x 16 diagonal block must be stored zeros -- and D stored
+// transposed (D(i, j) at C[j + i ldc]) if TOUT, else at C[i + j ldc].  One
+// wave per 16 x 16 tile, four per workgroup.
+template <bool AUP, bool BUP, bool TOUT>
+__global__ __launch_bounds__(256) void k_chain_nn(const double* __restrict__ A, int64_t lda,
+                                                  const double* __restrict__ B, int64_t ldb, int M, int N, int K,
+                                                  double alpha, double* __restrict__ C, int64_t ldc,
+                                                  const int32_t* __restrict__ info) {
   if (info != nullptr && *info != 0) return;
   const int lane = threadIdx.x & 63;
   const int t = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
@@ -230,15 +234,27 @@ __global__ __launch_bounds__(256) void k_chain_panel(const double* __restrict__ 
   if (16 * I >= M) return;  // past the last tile (wave-uniform; no barrier follows)
   const int r16 = lane & 15, k4 = lane >> 4;
   const int i = 16 * I + r16, j = 16 * J + r16;
-  const int ke = K < 16 * J + 16 ? K : 16 * J + 16;  // U(k, j) = 0 for k > j
+  const int kb = AUP ? 16 * I : 0;
+  const int ke = BUP ? (K < 16 * J + 16 ? K : 16 * J + 16) : K;
   const chain_d4 acc = chain_mfma(
-      0, ke, k4, [&](int k) { return i < M ? A[i + (int64_t)k * lda] : 0.0; },
-      [&](int k) { return j < N ? U[k + (int64_t)j * ldb] : 0.0; });
+      kb, ke, k4, [&](int k) { return i < M ? A[i + (int64_t)k * lda] : 0.0; },
+      [&](int k) { return j < N ? B[k + (int64_t)j * ldb] : 0.0; });
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int ii = 16 * I + 4 * r + k4, jj = 16 * J + r16;
-    if (ii < M && jj < N) C[jj + (int64_t)ii * ldc] = acc[r];
+    if (ii < M && jj < N) C[TOUT ? jj + (int64_t)ii * ldc : ii + (int64_t)jj * ldc] = alpha * acc[r];
   }
+}
+
+template <bool AUP, bool BUP, bool TOUT>
+static hipError_t launch_chain_nn(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t M, int64_t N,
+                                  int64_t K, double alpha, double* C, int64_t ldc, const int32_t* info,
+                                  hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  const int64_t tiles = ((M + 15) / 16) * ((N + 15) / 16);
+  hipLaunchKernelGGL((k_chain_nn<AUP, BUP, TOUT>), dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, s, A, lda, B,
+                     ldb, (int)M, (int)N, (int)K, alpha, C, ldc, info);
+  return hipGetLastError();
 }
 
 // C(i, j) -= sum_{k < K} A(k, i) A(k, j) for j <= i < M (A: K x M, lda; C: the
@@ -282,14 +298,11 @@ __global__ __launch_bounds__(256) void k_chain_diag(const double* __restrict__ A
 }
 
 // R_{k,>k} = R_kk^-T W_{>k,k}^T, computed as (W_{>k,k} R_kk^-1)ᵀ: Wb is the
-// r1 x bk block W_{>k,k} (ldw), Rikk the bk x bk upper R_kk^-1 (ldri), Rk1 the
-// bk x r1 block of R (ldr).
+// r1 x bk block W_{>k,k} (ldw), Rikk the bk x bk upper R_kk^-1 (ldri, zero
+// below its diagonal), Rk1 the bk x r1 block of R (ldr).
 static hipError_t launch_chain_panel(const double* Wb, int64_t ldw, const double* Rikk, int64_t ldri, int64_t r1,
                                      int64_t bk, double* Rk1, int64_t ldr, const int32_t* info, hipStream_t s) {
-  const int64_t tiles = ((r1 + 15) / 16) * ((bk + 15) / 16);
-  hipLaunchKernelGGL(k_chain_panel, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, s, Wb, ldw, Rikk, ldri,
-                     (int)r1, (int)bk, (int)bk, Rk1, ldr, info);
-  return hipGetLastError();
+  return launch_chain_nn<false, true, true>(Wb, ldw, Rikk, ldri, r1, bk, bk, 1.0, Rk1, ldr, info, s);
 }
 
 // W_d (n1 x n1, lower) -= Rdᵀ Rd for the kr x n1 block Rd of R (ldr).
@@ -400,7 +413,12 @@ static hipError_t cholinv_rec(double* W, int64_t ldw, int64_t n, double* R, int6
   const int sub = depth > 0 ? depth - 1 : 0;
   // leading diagonal block: its factor and inverse, recursively
   CQR2_HIP(cholinv_rec(W, ldw, h, R, ldr, Rinv, ldri, work, info, info_offset, s, sub));
-  if (depth == 0) {
+  // h = 128: the leading inverse is a base case (zero below its diagonal), and
+  // the products are small enough for the one-launch kernels
+  const bool small = h == kBaseN && n2 <= 3 * kBaseN;
+  if (depth == 0 && small) {
+    CQR2_HIP(launch_chain_panel(W + h, ldw, Rinv, ldri, n2, h, R12, ldr, info, s));
+  } else if (depth == 0) {
     // off-diagonal block of the factor from the leading inverse, kept transposed
     // in R's upper part: R12 = Rinv11ᵀ A21ᵀ
     CQR2_HIP(launch_gemm(1, 1, h, n2, h, 1.0, Rinv, ldri, W + h, ldw, 0.0, R12, ldr, GEMM_A_LOWER,
@@ -424,11 +442,19 @@ static hipError_t cholinv_rec(double* W, int64_t ldw, int64_t n, double* R, int6
     }
   }
   // trailing Schur complement (lower triangle): A22 - R12ᵀ R12
-  CQR2_HIP(launch_gemm(1, 0, n2, n2, h, -1.0, R12, ldr, R12, ldr, 1.0, W22, ldw, GEMM_C_LOWER,
-                       rec_splits(n2, n2, h), gws, info, s));
+  if (small)
+    CQR2_HIP(launch_chain_diag(R12, ldr, h, n2, W22, ldw, info, s));
+  else
+    CQR2_HIP(launch_gemm(1, 0, n2, n2, h, -1.0, R12, ldr, R12, ldr, 1.0, W22, ldw, GEMM_C_LOWER,
+                         rec_splits(n2, n2, h), gws, info, s));
   // trailing diagonal block: factor and inverse of the Schur complement
   CQR2_HIP(cholinv_rec(W22, ldw, n2, R22, ldr, Ri22, ldri, work, info, info_offset + (int)h, s, sub));
-  if (depth == 0) {
+  if (depth == 0 && small) {
+    // Rinv12 = -(Rinv11 R12) Rinv22; Rinv22's 16 x 16 diagonal blocks lie in
+    // its base cases' diagonal blocks (zero below the diagonal)
+    CQR2_HIP((launch_chain_nn<true, false, false>(Rinv, ldri, R12, ldr, h, n2, h, 1.0, T, h, info, s)));
+    CQR2_HIP((launch_chain_nn<false, true, false>(T, h, Ri22, ldri, h, n2, n2, -1.0, Ri12, ldri, info, s)));
+  } else if (depth == 0) {
     // off-diagonal block of the inverse from the two diagonal inverses and
     // R12: Rinv12 = -(Rinv11 R12) Rinv22
     CQR2_HIP(launch_gemm(0, 0, h, n2, h, 1.0, Rinv, ldri, R12, ldr, 0.0, T, h, GEMM_A_UPPER, rec_splits(h, n2, h),
@@ -707,10 +733,11 @@ hipError_t factor_general(const double* A, int64_t m, int64_t n, int64_t lda, do
   th.end(4, s);
   constexpr int kUp = GEMM_A_UPPER | GEMM_B_UPPER | GEMM_C_UPPER;
   if (!shifted) {
-    // R = R2 R1 (n > 256: the segmented tall kernel on R1's upper image)
+    // R = R2 R1 (both zero below the diagonal): n <= 256 one wave per 16 x 16
+    // tile, n > 256 the segmented tall kernel on R1's upper image
     th.begin(5, s);
     if (wide) {
-      CQR2_HIP(launch_gemm(0, 0, n, n, n, 1.0, R2, n, R1, n, 0.0, P, n, kUp, 1, nullptr, info, s));
+      CQR2_HIP((launch_chain_nn<true, true, false>(R2, n, R1, n, n, n, n, 1.0, P, n, info, s)));
     } else {
       CQR2_HIP(launch_upper_image(R1, n, (int)n, Uimg, s));
       CQR2_HIP(launch_upper_seg(R2, (int)n, n, Uimg, P, n, (double*)scratch, info, s));
