@@ -731,23 +731,26 @@ hipError_t factor_general(const double* A, int64_t m, int64_t n, int64_t lda, do
     CQR2_HIP(launch_tall_gemm(q1f, Q1, m, (int)n, m, Uimg, Q, ldq, info, s));
   }
   th.end(4, s);
-  constexpr int kUp = GEMM_A_UPPER | GEMM_B_UPPER | GEMM_C_UPPER;
+  // Z = X Y for n x n upper X (zero below its diagonal) and upper Y (read
+  // from its upper triangle only), Z's upper triangle: n <= 256 one wave per
+  // 16 x 16 tile (Z exactly upper; Y's 16 x 16 diagonal blocks read, zero
+  // below), n > 256 the segmented tall kernel on Y's upper image (Z's tiles
+  // wholly below the diagonal not written)
+  auto upper_times_upper = [&](const double* X, const double* Y, double* Z) -> hipError_t {
+    if (wide) return launch_chain_nn<true, true, false>(X, n, Y, n, n, n, n, 1.0, Z, n, info, s);
+    CQR2_HIP(launch_upper_image(Y, n, (int)n, Uimg, s));
+    return launch_upper_seg(X, (int)n, n, Uimg, Z, n, (double*)scratch, info, s);
+  };
   if (!shifted) {
-    // R = R2 R1 (both zero below the diagonal): n <= 256 one wave per 16 x 16
-    // tile, n > 256 the segmented tall kernel on R1's upper image
+    // R = R2 R1
     th.begin(5, s);
-    if (wide) {
-      CQR2_HIP((launch_chain_nn<true, true, false>(R2, n, R1, n, n, n, n, 1.0, P, n, info, s)));
-    } else {
-      CQR2_HIP(launch_upper_image(R1, n, (int)n, Uimg, s));
-      CQR2_HIP(launch_upper_seg(R2, (int)n, n, Uimg, P, n, (double*)scratch, info, s));
-    }
+    CQR2_HIP(upper_times_upper(R2, R1, P));
     CQR2_HIP(launch_finalize_r(P, n, R, ldr, n, info, d_info, s));
     th.end(5, s);
     return hipSuccess;
   }
   // shifted CholeskyQR3: a third pass on Q, then R = R3 (R2 R1)
-  CQR2_HIP(launch_gemm(0, 0, n, n, n, 1.0, R2, n, R1, n, 0.0, P, n, kUp, 1, nullptr, info, s));
+  CQR2_HIP(upper_times_upper(R2, R1, P));
   th.begin(0, s);
   if (wide)
     CQR2_HIP(launch_gram_wide(wp, 0, Q, m, (int)n, ldq, (double*)scratch, W, n, info, s));
@@ -768,7 +771,7 @@ hipError_t factor_general(const double* A, int64_t m, int64_t n, int64_t lda, do
   }
   th.end(4, s);
   th.begin(5, s);
-  CQR2_HIP(launch_gemm(0, 0, n, n, n, 1.0, R1, n, P, n, 0.0, W, n, kUp, 1, nullptr, info, s));
+  CQR2_HIP(upper_times_upper(R1, P, W));
   CQR2_HIP(launch_finalize_r(W, n, R, ldr, n, info, d_info, s));
   th.end(5, s);
   return hipSuccess;
