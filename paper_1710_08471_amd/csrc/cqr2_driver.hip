@@ -196,8 +196,9 @@ static hipError_t lookahead_events(LookaheadStreams& L, size_t count) {
 typedef double chain_d4 __attribute__((ext_vector_type(4)));
 constexpr int kChainBatch = 32;
 
-// acc += sum over k in [kb, ke) of opA(i, k) opB(k, j) for this lane's i, j;
-// ld(k, row) loads opA or opB (0 outside).
+// The 16 x 16 tile's sum over k in [kb, ke) of opA(i, k) opB(k, j), in the
+// result layout above; lda_(k) and ldb_(k) return this lane's opA(i, k) and
+// opB(k, j) (0 outside the matrices).
 template <typename LA, typename LB>
 __device__ __forceinline__ chain_d4 chain_mfma(int kb, int ke, int k4, LA lda_, LB ldb_) {
   chain_d4 acc = {0.0, 0.0, 0.0, 0.0};
