@@ -324,8 +324,8 @@ static hipError_t cholinv_lookahead(double* W, int64_t ldw, int64_t n, double* R
   const int64_t nb = (n + kBaseN - 1) / kBaseN;
   // events: P_k (base(k), and panel(k) when there is one, done), T1_k (B's
   // first part of update k done), and the joins of B and C.  Every event the
-  // caller's stream records or waits for costs the chain about 12 us, so the
-  // chain records one and waits for one per block.
+  // caller's stream records or waits for costs the chain about 6 us, even when
+  // already complete, so the chain records one and waits for one per block.
   CQR2_HIP(lookahead_events(L, (size_t)(2 * nb + 2)));
   hipEvent_t* evP = L.ev.data();
   hipEvent_t* evT1 = evP + nb;
