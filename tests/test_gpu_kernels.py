@@ -208,8 +208,10 @@ def test_upper_product_wide_integer_exact(gpu_lib, n):
 
 
 @pytest.mark.parametrize("n,kappa", [(129, 1e2), (200, 1e3), (256, 1e3), (300, 1e2),
+                                     # 511: the halving recursion's one-launch products at their largest (n2 = 383)
+                                     (511, 1e3),
                                      # n >= 512: the 128-column blocked form on three streams; whole and ragged last blocks
-                                     (520, 1e2), (640, 1e3), (1000, 1e2), (1153, 1e4)])
+                                     (512, 1e2), (520, 1e2), (640, 1e3), (1000, 1e2), (1153, 1e4)])
 def test_cholinv_recursive_random_spd(gpu_lib, n, kappa):
     a = gdv_matrix(2 * n + 7, n, kappa, seed=n)
     w = oracle.syrk(a)
